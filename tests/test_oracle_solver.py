@@ -1,0 +1,416 @@
+"""Pins of the CPU FP64 solver oracle against facts that do not come from the
+oracle itself: library solvers, closed-form solutions, exact discrete
+eigenmodes, conservation, the maximum principle and brute-force dense linear
+algebra.  Each test names the passage of the paper (Ayriyan & Busa, arXiv
+1912.03744) whose content it pins.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.special
+
+import oracle
+from paper_1912_03744_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_spec(nr=7, nz=12, h=(0.3, 0.2, math.inf, 0.15), t_inf=(0.4, -0.3, 0.25, 0.1),
+              q=(0.2, 0.0, 1.5, 0.3, 0.1), scheme="pr"):
+    """A small grid with every region, the cut-out, the terminal and all four
+    boundary classes active (non-zero T_inf, one Dirichlet class)."""
+    return W.Spec(r0=1.0, r1=1.6, r2=2.3, rmax=2.6, z0=3.1, zmax=4.4, ztop=5.0,
+                  nr=nr, nz=nz, h=h, t_inf=t_inf, k=(0.8, 0.07, 1.3, 0.2, 2.1),
+                  rhoc=(1.1, 0.6, 1.7, 0.9, 1.3), q=q, scheme=scheme)
+
+
+def dense_operators(P):
+    """L_r, b_r, L_z, b_z as dense matrices over all cells, obtained by
+    probing the affine operators with unit vectors."""
+    n = P.nr * P.nz
+    ar0, az0 = P.apply(np.zeros(n))
+    br, bz = ar0.ravel(), az0.ravel()
+    Lr, Lz = np.zeros((n, n)), np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        ar, az = P.apply(e)
+        Lr[:, c] = ar.ravel() - br
+        Lz[:, c] = az.ravel() - bz
+    return Lr, br, Lz, bz
+
+
+# ----------------------------------------------------------- Thomas (Sec. 3) --
+
+def test_thomas_matches_dense_lu():
+    """The line solver equals numpy's LU solve on diagonally dominant systems,
+    including identity rows that split a line (cut-out cells)."""
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 3, 17, 200):
+        a, c = -rng.uniform(0, 1, n), -rng.uniform(0, 1, n)
+        b = np.abs(a) + np.abs(c) + rng.uniform(0.01, 2.0, n)
+        if n > 4:
+            for i in (n // 3, n // 3 + 1):
+                a[i], b[i], c[i] = 0.0, 1.0, 0.0
+        d = rng.normal(size=n)
+        A = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        ref = np.linalg.solve(A, d)
+        x = oracle.thomas(a, b, c, d)
+        assert np.max(np.abs(x - ref)) <= 1e-14 * max(1.0, np.max(np.abs(ref)))
+
+
+# ------------------------------------------------ regions (Fig. 1, eq. 7) --
+
+def test_region_counts_single_layout():
+    """Cell counts per region of the 64 x 160 single layout, derived by hand
+    in the golden file from the centre rule."""
+    want = {}
+    with open(os.path.join(GOLDEN, "single_layout_region_counts.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                key, val = line.split("=")
+                want[key.strip()] = int(val)
+    P = oracle.Problem.from_spec(W.single_layout())
+    m = P.region_map()
+    got = {"cooler": int(np.sum(m == 0)), "insulator": int(np.sum(m == 1)),
+           "heater": int(np.sum(m == 2)), "outer_insulator": int(np.sum(m == 3)),
+           "terminal": int(np.sum(m == 4)), "masked": int(np.sum(m == 255))}
+    assert got == want
+
+
+# --------------------------------------- operator structure (eq. 10-11) --
+
+def test_operator_symmetry_and_null_space():
+    """The r-weighted balance operators are self-adjoint in the volume-weighted
+    inner product (V L symmetric), negative semi-definite, and annihilate
+    constants when every boundary film is zero.  A transposed index, a wrong
+    face radius or a sign error breaks one of these."""
+    s = tiny_spec(h=(0.0, 0.0, 0.0, 0.0), t_inf=(0.0,) * 4)
+    P = oracle.Problem.from_spec(s)
+    Lr, br, Lz, bz = dense_operators(P)
+    V = P.coeffs("V").ravel()
+    act = P.active().ravel()
+    for L in (Lr, Lz):
+        S = V[:, None] * L
+        assert np.max(np.abs(S - S.T)) <= 1e-13 * np.max(np.abs(S))
+        ev = np.linalg.eigvalsh(0.5 * (S + S.T)[np.ix_(act, act)])
+        assert ev.max() <= 1e-12 * np.abs(ev).max()
+        assert np.max(np.abs(L[np.ix_(act, act)] @ np.ones(act.sum()))) <= 1e-12 * np.abs(L).max()
+    assert np.all(br == 0) and np.all(bz == 0)
+
+
+def test_axial_cosine_mode_exact_eigenvector():
+    """In a homogeneous cylinder with insulated faces, cos(pi m z/Z) sampled at
+    the cell centres is an exact eigenvector of the cell-centred axial
+    operator with eigenvalue -(4k/dz^2) sin^2(pi m dz/(2Z)) (discrete Fourier
+    analysis of eq. 11)."""
+    k = 0.7
+    s = W.Spec(r0=0.5, r1=0.8, r2=1.0, rmax=1.2, z0=3.0, zmax=3.0, ztop=3.0, nr=5, nz=24,
+               h=(0.0,) * 4, t_inf=(0.0,) * 4, k=(k,) * 5, rhoc=(1.0,) * 5, q=(0.0,) * 5)
+    P = oracle.Problem.from_spec(s)
+    dz = 3.0 / 24
+    zc = (np.arange(24) + 0.5) * dz
+    for m in (1, 3, 7):
+        v = np.cos(np.pi * m * zc / 3.0)
+        T = np.tile(v[:, None], (1, 5))
+        _, az = P.apply(T)
+        mu = -(4 * k / dz**2) * np.sin(np.pi * m * dz / 6.0) ** 2
+        assert np.max(np.abs(az - mu * T)) <= 1e-12 * abs(mu)
+
+
+# ---------------------------------------------- time stepping (eq. 8-9) --
+
+def dense_step(P, s, T, scheme, dt):
+    """One ADI step by dense linear algebra over all cells."""
+    Lr, br, Lz, bz = dense_operators(P)
+    C = P.coeffs("C").ravel()
+    Q = P.coeffs("Q").ravel()
+    act = P.active().ravel()
+    n = T.size
+    ta = 0.5 * dt if scheme == "pr" else dt
+    th = 1.0 if scheme == "pr" else 0.0
+    D = np.diag(np.where(act, C / ta, 1.0))
+    T = T.ravel()
+    rhs1 = np.where(act, C / ta * T + th * (Lz @ T + bz) + Q + br, 0.0)
+    Tb = np.linalg.solve(D - Lr, rhs1)
+    rhs2 = np.where(act, C / ta * Tb + th * (Lr @ Tb + br + Q) + bz, 0.0)
+    Th = np.linalg.solve(D - Lz, rhs2)
+    assert n == Th.size
+    return Th.reshape(P.shape), Tb.reshape(P.shape)
+
+
+@pytest.mark.parametrize("scheme", ["pr", "lod"])
+def test_one_step_matches_dense_solve(scheme):
+    """Line-by-line Thomas sweeps equal a dense solve of the same half-step
+    systems (eq. 8-9; masked cells as identity rows)."""
+    s = tiny_spec(scheme=scheme)
+    P = oracle.Problem.from_spec(s)
+    rng = np.random.default_rng(1)
+    T = np.where(P.active(), rng.normal(size=P.shape), 0.0)
+    dt = 0.05
+    got, got_mid = P.step(T, scheme, dt, 1)
+    want, want_mid = dense_step(P, s, T, scheme, dt)
+    scale = np.max(np.abs(want))
+    assert np.max(np.abs(got - want)) <= 1e-13 * scale
+    assert np.max(np.abs(got_mid - want_mid)) <= 1e-13 * scale
+
+
+def test_pr_fixed_point_is_discrete_steady_state():
+    """The steady solution of (L_r + L_z) T + b + Q = 0 is a fixed point of
+    Peaceman-Rachford for any step size (eq. 8-9 at T = Tbar = That)."""
+    s = tiny_spec()
+    P = oracle.Problem.from_spec(s)
+    Lr, br, Lz, bz = dense_operators(P)
+    act = P.active().ravel()
+    Q = P.coeffs("Q").ravel()
+    A = (Lr + Lz)[np.ix_(act, act)]
+    Ts = np.zeros(act.size)
+    Ts[act] = np.linalg.solve(A, -(br + bz + Q)[act])
+    for dt in (1e-3, 0.3, 40.0):
+        got, _ = P.step(Ts, "pr", dt, 1)
+        assert np.max(np.abs(got.ravel() - Ts)) <= 1e-12 * np.max(np.abs(Ts))
+
+
+def test_lod_fixed_point():
+    """LOD backward Euler keeps T fixed iff (L_r + L_z - tau L_r C^-1 L_z) T =
+    -(b_r + b_z + Q) + tau L_r C^-1 b_z (eliminate the intermediate field)."""
+    s = tiny_spec(scheme="lod")
+    P = oracle.Problem.from_spec(s)
+    Lr, br, Lz, bz = dense_operators(P)
+    act = P.active().ravel()
+    C = np.where(act, P.coeffs("C").ravel(), 1.0)
+    Q = P.coeffs("Q").ravel()
+    dt = 0.2
+    Ci = np.diag(1.0 / C)
+    A = Lr + Lz - dt * Lr @ Ci @ Lz
+    rhs = -(br + bz + Q) + dt * Lr @ (bz / C)
+    T = np.zeros(act.size)
+    T[act] = np.linalg.solve(A[np.ix_(act, act)], rhs[act])
+    got, _ = P.step(T, "lod", dt, 1)
+    assert np.max(np.abs(got.ravel() - T)) <= 1e-12 * np.max(np.abs(T))
+
+
+def test_separable_mode_decays_by_exact_amplification():
+    """Homogeneous insulated cylinder: a product of an r-eigenvector of the
+    radial operator and the axial cosine mode is multiplied each step by
+    (1+tau mu_r/2)(1+tau mu_z/2)/((1-tau mu_r/2)(1-tau mu_z/2)) under PR and
+    by 1/((1-tau mu_r)(1-tau mu_z)) under LOD-BE; checked after 1000 steps."""
+    k, rc_ = 0.9, 1.3
+    s = W.Spec(r0=0.5, r1=0.8, r2=1.0, rmax=1.2, z0=2.0, zmax=2.0, ztop=2.0, nr=12, nz=16,
+               h=(0.0,) * 4, t_inf=(0.0,) * 4, k=(k,) * 5, rhoc=(rc_,) * 5, q=(0.0,) * 5)
+    P = oracle.Problem.from_spec(s)
+    # radial operator from one row, made symmetric with W = r dr
+    n = s.nr
+    Lr1 = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(P.shape)
+        e[0, c] = 1.0
+        ar, _ = P.apply(e)
+        Lr1[:, c] = ar[0]
+    rf, zf, rc, zc = P.grid()
+    w = rc * np.diff(rf)
+    S = np.diag(np.sqrt(w)) @ Lr1 @ np.diag(1 / np.sqrt(w))
+    evals, evecs = scipy.linalg.eigh(0.5 * (S + S.T))
+    dz = 2.0 / 16
+    for (ir, m) in ((n - 2, 1), (n - 4, 2)):
+        vr = evecs[:, ir] / np.sqrt(w)
+        mu_r = evals[ir] / rc_
+        mu_z = -(4 * k / (rc_ * dz**2)) * np.sin(np.pi * m * dz / 4.0) ** 2
+        vz = np.cos(np.pi * m * zc / 2.0)
+        T0 = np.outer(vz, vr)
+        for scheme, dt in (("pr", 1e-4), ("lod", 1e-4)):
+            if scheme == "pr":
+                g = ((1 + dt * mu_r / 2) * (1 + dt * mu_z / 2)) / ((1 - dt * mu_r / 2) * (1 - dt * mu_z / 2))
+            else:
+                g = 1.0 / ((1 - dt * mu_r) * (1 - dt * mu_z))
+            got, _ = P.step(T0, scheme, dt, 1000)
+            want = g**1000 * T0
+            assert 1e-3 < abs(g**1000) < 1.0
+            assert np.max(np.abs(got - want)) <= 1e-13 * 1000 * np.max(np.abs(T0))
+
+
+def _bessel_error(n, dt, t_end):
+    R, Z, k, rc_ = 1.0, 1.0, 1.0, 1.0
+    s = W.Spec(r0=0.4, r1=0.6, r2=0.8, rmax=R, z0=Z, zmax=Z, ztop=Z, nr=n, nz=n,
+               h=(0.0,) * 4, t_inf=(0.0,) * 4, k=(k,) * 5, rhoc=(rc_,) * 5, q=(0.0,) * 5)
+    P = oracle.Problem.from_spec(s)
+    _, _, rc, zc = P.grid()
+    a = scipy.special.jn_zeros(1, 1)[0] / R
+    b = np.pi / Z
+    T0 = np.outer(np.cos(b * zc), scipy.special.j0(a * rc))
+    steps = int(round(t_end / dt))
+    got, _ = P.step(T0, "pr", dt, steps)
+    exact = np.exp(-(k / rc_) * (a * a + b * b) * t_end) * T0
+    return np.max(np.abs(got - exact))
+
+
+def test_bessel_cosine_mode_second_order():
+    """J0(alpha r) cos(beta z) exp(-kappa (alpha^2+beta^2) t) solves eq. 1 with
+    insulated faces when alpha R is the first zero of J1.  PR on the cell-
+    centred r-weighted operator converges at second order in (h, tau)."""
+    errs = [_bessel_error(n, 0.02 * 16 / n, 0.08) for n in (16, 32, 64)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.5 < r2 < 4.6, errs
+
+
+# --------------------- interface conductance and Robin film (eq. 6, 10) --
+
+def _radial_steady(counts, source_region, h_out=0.7, t_inf=0.3):
+    r0, r1, r2, rmax = 0.6, 0.9, 1.3, 1.5
+    k = (2.0, 0.1, 1.2, 0.3, 1.0)
+    Q = 1.7
+    rf = W.layer_aligned_faces((0.0, r0, r1, r2, rmax), counts)
+    q = [0.0] * 5
+    q[source_region] = Q
+    s = W.Spec(r0=r0, r1=r1, r2=r2, rmax=rmax, z0=1.0, zmax=1.0, ztop=1.0,
+               nr=len(rf) - 1, nz=1, h=(0.0, h_out, 0.0, 0.0), t_inf=(0.0, t_inf, 0.0, 0.0),
+               k=k, rhoc=(1.0,) * 5, q=tuple(q), r_faces=rf)
+    P = oracle.Problem.from_spec(s)
+    Lr, br, Lz, bz = dense_operators(P)
+    Qv = P.coeffs("Q").ravel()
+    T = np.linalg.solve(Lr + Lz, -(br + bz + Qv))
+    _, _, rc, _ = P.grid()
+    rho = (r0, r1, r2, rmax)
+    if source_region == 0:
+        phi = Q * r0**2 / 2
+    else:
+        phi = Q * (r2**2 - r1**2) / 2
+    Tmax = t_inf + phi / (rmax * h_out)
+
+    def outer(r, m):  # log-resistance series from shell m (region m+1) outwards
+        v = Tmax + phi * np.log(rho[m + 1] / r) / k[m + 1]
+        for mm in range(m + 1, 3):
+            v += phi * np.log(rho[mm + 1] / rho[mm]) / k[mm + 1]
+        return v
+
+    exact = np.empty_like(rc)
+    for i, r in enumerate(rc):
+        if r < r0:
+            if source_region == 0:
+                exact[i] = outer(r0, 0) + Q * (r0**2 - r**2) / (4 * k[0])
+            else:
+                exact[i] = ring_T(r1, r1, r2, Q, k[2], outer(r2, 2))
+        elif r < r1:
+            exact[i] = outer(r, 0) if source_region == 0 else ring_T(r1, r1, r2, Q, k[2], outer(r2, 2))
+        elif r < r2:
+            exact[i] = outer(r, 1) if source_region == 0 else ring_T(r, r1, r2, Q, k[2], outer(r2, 2))
+        else:
+            exact[i] = outer(r, 2)
+    return T, exact, rc
+
+
+def ring_T(r, r1, r2, Q, k, T_r2):
+    return T_r2 + (Q / (2 * k)) * ((r2**2 - r**2) / 2 - r1**2 * np.log(r2 / r))
+
+
+@pytest.mark.parametrize("source_region", [0, 2])
+def test_concentric_layers_log_resistance(source_region):
+    """Steady radial conduction through the concentric layers (series
+    logarithmic resistances plus the Robin film at rmax) is reproduced at
+    second order on layer-aligned grids; an arithmetic-mean face
+    conductivity would only give first order."""
+    errs = []
+    for f in (1, 2, 4):
+        T, exact, _ = _radial_steady((6 * f, 4 * f, 5 * f, 3 * f), source_region)
+        errs.append(np.max(np.abs(T - exact)) / np.max(np.abs(exact)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.3 < r1 < 4.7 and 3.3 < r2 < 4.7, errs
+
+
+def test_axis_regularity_quadratic_core():
+    """Around r = 0 the steady core solution is the quadratic
+    T0 - Q r^2/(4k); the cell-centred scheme reproduces it exactly, so
+    (T_1 - T_0)/(T_2 - T_0) = (r_1^2 - r_0^2)/(r_2^2 - r_0^2) = 1/3 on a
+    uniform core grid, and the axis face carries no flux."""
+    for f in (1, 3):
+        T, _, rc = _radial_steady((6 * f, 4 * f, 5 * f, 3 * f), 0)
+        assert abs((T[1] - T[0]) / (T[2] - T[0]) - 1.0 / 3.0) < 1e-9
+
+
+# --------------------------------------------------- conservation (a5) --
+
+@pytest.mark.parametrize("scheme", ["pr", "lod"])
+def test_energy_identity_each_half_step(scheme):
+    """Summing the balance form of eq. 8-9 over all cells telescopes the
+    interior fluxes: the heat content changes only by source work and the
+    boundary flows, at the time levels at which each operator is taken."""
+    s = tiny_spec(nr=9, nz=14, scheme=scheme)
+    P = oracle.Problem.from_spec(s)
+    rng = np.random.default_rng(5)
+    T = np.where(P.active(), rng.uniform(-1, 2, size=P.shape), 0.0)
+    dt = 0.03
+    Th, Tb = P.step(T, scheme, dt, 1)
+    e0, eb, eh = P.energy(T), P.energy(Tb), P.energy(Th)
+    Pw = e0["P"]
+    if scheme == "pr":
+        ta = dt / 2
+        lhs1, rhs1 = eb["E"] - e0["E"], ta * (Pw - eb["Br"] - e0["Bz"])
+        lhs2, rhs2 = eh["E"] - eb["E"], ta * (Pw - eb["Br"] - eh["Bz"])
+    else:
+        lhs1, rhs1 = eb["E"] - e0["E"], dt * (Pw - eb["Br"])
+        lhs2, rhs2 = eh["E"] - eb["E"], -dt * eh["Bz"]
+    scale = sum(abs(x) for x in (e0["E"], eb["E"], eh["E"])) + dt * (abs(Pw) + abs(eb["Br"]) + abs(e0["Bz"]) + abs(eh["Bz"]))
+    assert abs(lhs1 - rhs1) <= 1e-12 * scale
+    assert abs(lhs2 - rhs2) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("scheme", ["pr", "lod"])
+def test_uniform_heating(scheme):
+    """One material, uniform source, insulated faces: T = T0 + Q t / (rho c)
+    in every cell, cut-out faces included."""
+    s = W.single_layout(nr=10, nz=20).replace(
+        k=(0.4,) * 5, rhoc=(1.7,) * 5, q=(0.9,) * 5, h=(0.0,) * 4, scheme=scheme)
+    P = oracle.Problem.from_spec(s)
+    T0 = P.initial(0.25)
+    dt, n = 0.01, 37
+    got, _ = P.step(T0, scheme, dt, n)
+    act = P.active()
+    want = 0.25 + 0.9 * dt * n / 1.7
+    assert np.max(np.abs(got[act] - want)) <= 1e-14 * 10 * want * n
+    assert np.all(got[~act] == 0.0)
+
+
+def test_maximum_principle():
+    """Q >= 0 with T0 = T_inf = 0 keeps T >= 0: always for LOD-BE (inverse of
+    an M-matrix is non-negative), and for PR when the explicit half is
+    monotone (the single layout at dt = 1e-3).  With Q = 0 the maximum never
+    grows."""
+    s = W.single_layout(nr=32, nz=80)
+    P = oracle.Problem.from_spec(s)
+    T = P.initial(0.0)
+    for scheme, dt in (("lod", 1e-3), ("lod", 0.5), ("pr", 1e-3)):
+        got, mid = P.step(T, scheme, dt, 50)
+        assert got.min() >= 0.0 and mid.min() >= 0.0
+    s0 = s.replace(q=(0.0,) * 5)
+    P0 = oracle.Problem.from_spec(s0)
+    rng = np.random.default_rng(2)
+    T = np.where(P0.active(), rng.uniform(0, 1, size=P0.shape), 0.0)
+    m = T.max()
+    for _ in range(5):
+        T, _ = P0.step(T, "lod", 0.2, 3)
+        assert T.max() <= m * (1 + 1e-15)
+        m = T.max()
+
+
+def test_profile_resampling():
+    """The 64-point terminal-face profile is the top row itself when nr = 64
+    and a linear interpolation between centres otherwise."""
+    s = W.single_layout()
+    P = oracle.Problem.from_spec(s)
+    rng = np.random.default_rng(0)
+    T = np.where(P.active(), rng.normal(size=P.shape), 0.0)
+    assert np.array_equal(P.profile(T, 0, 64), T[-1])
+    s2 = W.single_layout(nr=50, nz=40)
+    P2 = oracle.Problem.from_spec(s2)
+    _, _, rc, _ = P2.grid()
+    row = 3.0 * rc + 1.0
+    T2 = np.zeros(P2.shape)
+    T2[-1] = row
+    prof = P2.profile(T2, 0, 64)
+    rk = (np.arange(64) + 0.5) * s2.rmax / 64
+    want = np.interp(rk, rc, row)
+    assert np.max(np.abs(prof - want)) <= 1e-13
