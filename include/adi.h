@@ -1,0 +1,182 @@
+/*
+ * adi.h -- C ABI of libadi, an MI355X (gfx950) implementation of the
+ * alternating-direction-implicit (ADI) solver for the axisymmetric heat
+ * equation in a layered cylinder, after A. Ayriyan and J. Busa Jr.,
+ * "Parallel Algorithm for Numerical Solution of Heat Equation in Complex
+ * Cylindrical Domain" (arXiv 1912.03744), plus the batched design-sweep path
+ * and the learned surrogate built on it.
+ *
+ * Conventions
+ *  - Every call returns an adi_status; nothing throws or aborts across the
+ *    ABI.  adi_last_error() gives a thread-local message for the last failure.
+ *  - Fields are double, row-major with r fastest: cell (i, j) of an nr x nz
+ *    grid is element j*nr + i.  Region ids: 0 cooler, 1 inner insulator,
+ *    2 heater, 3 outer insulator, 4 terminal, 255 outside the domain.
+ *  - The library owns every device buffer it allocates (hipMalloc) and frees
+ *    it in the matching destroy call.  Host buffers belong to the caller and
+ *    are only read or written during the call.
+ *  - Work is enqueued on the HIP stream given at creation; NULL makes the
+ *    handle create (and later destroy) a non-blocking stream of its own, so
+ *    that its steps can be captured into HIP graphs.  Calls that return host
+ *    data synchronise that stream.
+ *    Asynchronous failures (non-finite values, energy-balance violations) are
+ *    latched on the device and reported by the next synchronising call.
+ *  - A handle is bound to one stream and is not thread-safe.
+ */
+#ifndef ADI_H
+#define ADI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADI_OK = 0,
+  ADI_EINVAL = -1,       /* invalid argument (message says which) */
+  ADI_ENOMEM = -2,       /* device or host allocation failed */
+  ADI_EDEVICE = -3,      /* a HIP runtime call failed */
+  ADI_ESTATE = -4,       /* call not allowed in the handle's current state */
+  ADI_ENONFINITE = -5,   /* a NaN/Inf appeared in the field or an input */
+  ADI_EBALANCE = -6,     /* the discrete energy identity was violated */
+  ADI_EUNSUPPORTED = -7  /* combination not supported by this build */
+} adi_status;
+
+/* Time integrator.
+ * ADI_PR: Peaceman-Rachford half steps of Sec. 3, eq. 8-9: r implicit / z
+ *   explicit over tau/2, then z implicit / r explicit over tau/2; the source
+ *   enters both half steps.
+ * ADI_LOD_BE: locally one-dimensional backward Euler (Yanenko splitting, cited
+ *   in Sec. 3): r implicit over tau with the source, then z implicit over tau. */
+typedef enum { ADI_PR = 0, ADI_LOD_BE = 1 } adi_scheme;
+
+/* Geometry of Fig. 1 (Sec. 2): cooler r < r0 for z < zmax; inner insulator
+ * r0 <= r < r1, heater r1 <= r < r2, outer insulator r2 <= r < rmax, all three
+ * for z < z0; terminal slab zmax <= z < ztop over the whole radius; cells with
+ * r >= r0 and z0 <= z < zmax are outside the domain.  Requires
+ * 0 < r0 <= r1 <= r2 <= rmax and 0 < z0 <= zmax <= ztop.
+ * Grid (eq. 7): cell-centred, nr x nz cells (1 <= nr, nz; nr*nz < 2^31).
+ * r_faces / z_faces: optional monotone face coordinates (nr+1 / nz+1 values,
+ * first 0, last rmax / ztop), copied at creation; NULL gives the uniform grid
+ * r_face[i] = rmax*i/nr, r_centre[i] = (i+0.5)*rmax/nr (same in z with ztop).
+ * A cell belongs to the region containing its centre. */
+typedef struct {
+  double r0, r1, r2, rmax;
+  double z0, zmax, ztop;
+  int32_t nr, nz;
+  const double* r_faces;
+  const double* z_faces;
+} adi_geometry;
+
+/* Boundary films (eq. 6 generalised to Robin): face classes 0 = bottom z = 0,
+ * 1 = outer r = rmax, 2 = top z = ztop, 3 = faces against cells outside the
+ * domain.  The flux out of cell c through such a face is g (T_c - t_inf) with
+ * g = 1/(d_c/(2 k_c) + 1/h): h = 0 is an insulated face, h = INFINITY fixes
+ * the face temperature to t_inf.  The axis r = 0 never carries flux.
+ * Requires h >= 0 (INFINITY allowed) and finite t_inf. */
+typedef struct {
+  double h[4];
+  double t_inf[4];
+} adi_bc;
+
+typedef struct adi_problem_s* adi_problem;
+typedef struct adi_batch_s* adi_batch;
+typedef struct adi_mlp_s* adi_mlp;
+
+/* Energy bookkeeping (2 pi dropped): E = sum rho c T V over active cells with
+ * V = r_c dr dz; source_power = sum Q V; boundary_flow = heat flow out through
+ * all boundary faces at the current field; residual = largest relative
+ * violation of the per-step energy identity seen by the periodic checks
+ * (0 if none ran); checks = number of periodic checks run. */
+typedef struct {
+  double E, E0, source_power, boundary_flow, residual, time;
+  int64_t steps, checks;
+} adi_energy_report;
+
+/* ------------------------------------------------------------ problems -- */
+
+/* Create a single-instance problem.  hip_stream: a hipStream_t (may be NULL).
+ * Allocates the field and work buffers on the current HIP device.
+ * Errors: ADI_EINVAL (geometry/bc), ADI_ENOMEM, ADI_EDEVICE. */
+adi_status adi_create_problem(const adi_geometry* g, const adi_bc* bc, adi_scheme scheme,
+                              void* hip_stream, adi_problem* out);
+
+/* Per-region conductivity k[5] and volumetric heat capacity rho_c[5]
+ * (eq. 1 with constant coefficients).  Both > 0 and finite. */
+adi_status adi_set_materials(adi_problem p, const double k[5], const double rho_c[5]);
+
+/* Per-region volumetric source Q[5] (eq. 2 with a constant source); finite. */
+adi_status adi_set_sources(adi_problem p, const double q[5]);
+
+/* Set the field: host_T (nz*nr doubles, values outside the domain ignored) or,
+ * if host_T is NULL, the uniform initial condition T0 of eq. 5.  Resets the
+ * step counter, the time and E0. */
+adi_status adi_set_field(adi_problem p, const double* host_T, double T0);
+
+/* Advance nsteps >= 0 steps of size dt > 0 (asynchronous on the stream).
+ * Requires materials and sources (else ADI_ESTATE).  Line solves use the
+ * factor tables of the current (dt, materials); they are rebuilt on the
+ * device when either changes. */
+adi_status adi_step(adi_problem p, double dt, int64_t nsteps);
+
+/* Run the discrete energy-identity check every `every` steps (0 = never) and
+ * latch ADI_EBALANCE when the relative residual exceeds tol (> 0). */
+adi_status adi_set_check(adi_problem p, int32_t every, double tol);
+
+/* Copy the field to host_out (count must equal nz*nr); cells outside the
+ * domain read as NaN.  Synchronises; returns a latched error if any. */
+adi_status adi_read_field(adi_problem p, double* host_out, size_t count);
+
+/* Enqueue a device-to-device copy of the field (nz*nr doubles, cells outside
+ * the domain hold 0) into dev_out. */
+adi_status adi_read_field_device(adi_problem p, void* dev_out);
+
+/* Region id per cell (count = nz*nr), computed on the device.  Synchronises. */
+adi_status adi_read_region_map(adi_problem p, uint8_t* host_out, size_t count);
+
+/* Temperature profile along one row, resampled at r_k = (k+0.5)*rmax/npts by
+ * linear interpolation between cell centres (constant beyond the first and
+ * last centre).  which = 0: top row (outer face of the terminal); which = 1:
+ * first row inside the terminal (contact face).  The row must lie inside the
+ * domain everywhere (ADI_EINVAL otherwise).  Synchronises. */
+adi_status adi_read_profile(adi_problem p, int32_t which, int32_t npts, double* host_out);
+
+/* Energy report of the current field.  Synchronises. */
+adi_status adi_energy(adi_problem p, adi_energy_report* out);
+
+/* Kernel timing for the roofline report: launches the r sweep nlaunch times,
+ * then the z sweep nlaunch times, each bracketed by HIP events on the
+ * problem's stream, and returns the mean duration per launch in ms.  The
+ * field is left unchanged.  Synchronises. */
+adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_r, float* ms_z);
+
+/* Launch shape of the line solves (advanced; the autotuner uses it).
+ * dir 0 = r lines, 1 = z lines.  chunk: cells per lane (3..48);
+ * lines_per_wave: 1, 2, 4, 8 or 16 (lanes of a wave split into this many
+ * lines); waves_per_line: 1, 2, 4, 8 or 16; groups_per_block: line groups
+ * per workgroup (1..16, at most 1024 threads).  The chunk count
+ * (64/lines_per_wave)*waves_per_line times chunk must cover the line length.
+ * ADI_EUNSUPPORTED if this build has no kernel for the shape. */
+adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lines_per_wave,
+                          int32_t waves_per_line, int32_t groups_per_block);
+adi_status adi_get_launch(adi_problem p, int32_t dir, int32_t* chunk, int32_t* lines_per_wave,
+                          int32_t* waves_per_line, int32_t* groups_per_block);
+
+/* Steps per captured HIP graph in adi_step (0 = plain launches). */
+adi_status adi_set_graph_steps(adi_problem p, int32_t steps);
+
+void adi_destroy(adi_problem p);
+
+/* ---------------------------------------------------------- utilities -- */
+
+const char* adi_status_string(adi_status s);
+const char* adi_last_error(void);
+/* Library version string. */
+const char* adi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADI_H */

@@ -1,0 +1,237 @@
+"""ctypes binding of libadi.so (include/adi.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of the library; this module
+converts Python values to the C ABI and raises on error codes.  The library
+must have been built (``python -m paper_1912_03744_amd.build``); loading
+fails loudly otherwise.  torch is imported first so that the library binds
+to the HIP runtime torch already uses (one runtime per process, so torch
+streams and device pointers can be passed in).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:  # torch provides device memory and streams to callers; load its HIP runtime first
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadi.so")
+
+ADI_OK, ADI_EINVAL, ADI_ENOMEM, ADI_EDEVICE, ADI_ESTATE = 0, -1, -2, -3, -4
+ADI_ENONFINITE, ADI_EBALANCE, ADI_EUNSUPPORTED = -5, -6, -7
+SCHEMES = {"pr": 0, "lod": 1}
+
+
+class AdiError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, message))
+        self.status = status
+
+
+_STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ENONFINITE",
+           -6: "EBALANCE", -7: "EUNSUPPORTED"}
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("r0", ctypes.c_double), ("r1", ctypes.c_double), ("r2", ctypes.c_double),
+                ("rmax", ctypes.c_double), ("z0", ctypes.c_double), ("zmax", ctypes.c_double),
+                ("ztop", ctypes.c_double), ("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("r_faces", ctypes.POINTER(ctypes.c_double)),
+                ("z_faces", ctypes.POINTER(ctypes.c_double))]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double * 4), ("t_inf", ctypes.c_double * 4)]
+
+
+class EnergyReport(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("E0", ctypes.c_double), ("source_power", ctypes.c_double),
+                ("boundary_flow", ctypes.c_double), ("residual", ctypes.c_double),
+                ("time", ctypes.c_double), ("steps", ctypes.c_int64), ("checks", ctypes.c_int64)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+# name -> argtypes (restype adi_status = int unless listed otherwise)
+_SIGS = {
+    "adi_create_problem": [ctypes.POINTER(Geometry), ctypes.POINTER(BC), ctypes.c_int, _vp,
+                           ctypes.POINTER(_vp)],
+    "adi_set_materials": [_vp, _dp, _dp],
+    "adi_set_sources": [_vp, _dp],
+    "adi_set_field": [_vp, _dp, ctypes.c_double],
+    "adi_step": [_vp, ctypes.c_double, ctypes.c_int64],
+    "adi_set_check": [_vp, ctypes.c_int32, ctypes.c_double],
+    "adi_read_field": [_vp, _dp, ctypes.c_size_t],
+    "adi_read_field_device": [_vp, _vp],
+    "adi_read_region_map": [_vp, ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t],
+    "adi_read_profile": [_vp, ctypes.c_int32, ctypes.c_int32, _dp],
+    "adi_energy": [_vp, ctypes.POINTER(EnergyReport)],
+    "adi_time_sweeps": [_vp, ctypes.c_double, ctypes.c_int32, _fp, _fp],
+    "adi_set_launch": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                       ctypes.c_int32],
+    "adi_get_launch": [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p],
+    "adi_set_graph_steps": [_vp, ctypes.c_int32],
+    "adi_destroy": [_vp],
+    "adi_status_string": [ctypes.c_int],
+    "adi_last_error": [],
+    "adi_version": [],
+}
+_RESTYPE = {"adi_destroy": None, "adi_status_string": ctypes.c_char_p,
+            "adi_last_error": ctypes.c_char_p, "adi_version": ctypes.c_char_p}
+
+_LIB = None
+
+
+def lib():
+    """Load libadi.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libadi.so is not built: run `python -m paper_1912_03744_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _RESTYPE.get(name, ctypes.c_int)
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def check(status):
+    if status != ADI_OK:
+        raise AdiError(status, lib().adi_last_error().decode())
+    return status
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def current_stream():
+    """The current torch stream as a hipStream_t, or None (the library then
+    uses a stream of its own) when torch has no GPU or is on its default
+    stream, which cannot be captured into a graph."""
+    if torch is not None and torch.cuda.is_available():
+        s = torch.cuda.current_stream().cuda_stream
+        return ctypes.c_void_p(s) if s else None
+    return None
+
+
+class Problem:
+    """One single-instance problem on the GPU (adi_create_problem ...)."""
+
+    def __init__(self, geom, nr, nz, h, t_inf, scheme="pr", r_faces=None, z_faces=None, stream=None):
+        r0, r1, r2, rmax, z0, zmax, ztop = (float(x) for x in geom)
+        self.nr, self.nz = int(nr), int(nz)
+        self._rf = None if r_faces is None else _f64(r_faces, self.nr + 1)
+        self._zf = None if z_faces is None else _f64(z_faces, self.nz + 1)
+        g = Geometry(r0, r1, r2, rmax, z0, zmax, ztop, self.nr, self.nz,
+                     _ptr(self._rf), _ptr(self._zf))
+        bc = BC((ctypes.c_double * 4)(*[float(x) for x in h]),
+                (ctypes.c_double * 4)(*[float(x) for x in t_inf]))
+        h_ = _vp()
+        st = stream if stream is not None else current_stream()
+        check(lib().adi_create_problem(ctypes.byref(g), ctypes.byref(bc), SCHEMES[scheme], st,
+                                       ctypes.byref(h_)))
+        self._h = h_
+        self.scheme = scheme
+
+    @classmethod
+    def from_spec(cls, s, stream=None):
+        p = cls(s.geom, s.nr, s.nz, s.h, s.t_inf, s.scheme, s.r_faces, s.z_faces, stream)
+        p.set_materials(s.k, s.rhoc)
+        p.set_sources(s.q)
+        p.set_field(None, s.T0)
+        return p
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().adi_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def shape(self):
+        return (self.nz, self.nr)
+
+    def set_materials(self, k, rhoc):
+        check(lib().adi_set_materials(self._h, _ptr(_f64(k, 5)), _ptr(_f64(rhoc, 5))))
+
+    def set_sources(self, q):
+        check(lib().adi_set_sources(self._h, _ptr(_f64(q, 5))))
+
+    def set_field(self, T=None, T0=0.0):
+        a = None if T is None else _f64(T, self.nr * self.nz)
+        check(lib().adi_set_field(self._h, _ptr(a), float(T0)))
+
+    def step(self, dt, nsteps):
+        check(lib().adi_step(self._h, float(dt), int(nsteps)))
+
+    def set_check(self, every, tol=1e-9):
+        check(lib().adi_set_check(self._h, int(every), float(tol)))
+
+    def set_graph_steps(self, steps):
+        check(lib().adi_set_graph_steps(self._h, int(steps)))
+
+    def read_field(self):
+        out = np.empty(self.shape)
+        check(lib().adi_read_field(self._h, _ptr(out), out.size))
+        return out
+
+    def read_field_device(self, dev_ptr):
+        check(lib().adi_read_field_device(self._h, ctypes.c_void_p(dev_ptr)))
+
+    def region_map(self):
+        out = np.empty(self.shape, dtype=np.uint8)
+        check(lib().adi_read_region_map(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                        out.size))
+        return out
+
+    def profile(self, which=0, npts=64):
+        out = np.empty(npts)
+        check(lib().adi_read_profile(self._h, int(which), int(npts), _ptr(out)))
+        return out
+
+    def energy(self):
+        r = EnergyReport()
+        check(lib().adi_energy(self._h, ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in EnergyReport._fields_}
+
+    def time_sweeps(self, dt, nlaunch):
+        a, b = ctypes.c_float(), ctypes.c_float()
+        check(lib().adi_time_sweeps(self._h, float(dt), int(nlaunch), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_launch(self, direction, chunk, lines_per_wave, waves_per_line, groups_per_block=1):
+        check(lib().adi_set_launch(self._h, int(direction), int(chunk), int(lines_per_wave),
+                                   int(waves_per_line), int(groups_per_block)))
+
+    def get_launch(self, direction):
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(lib().adi_get_launch(self._h, int(direction), *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+
+def version():
+    return lib().adi_version().decode()
+

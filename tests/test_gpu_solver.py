@@ -1,0 +1,184 @@
+"""GPU parity of the HIP ADI solver against the CPU FP64 oracle, element by
+element on the same seeded inputs (infinity-norm relative error over active
+cells <= 1e-12), plus region maps (bit-exact), profiles, energy and the
+launch shapes the autotuner can pick."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import gpu_available, rel_inf, run_gpu, run_oracle, tiny_spec
+from paper_1912_03744_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("spec", [tiny_spec(), W.single_layout(), W.production(0, nr=300, nz=700),
+                                  W.production(1)],
+                         ids=["tiny", "single", "mid", "production"])
+def test_region_map_bit_exact(spec):
+    from paper_1912_03744_amd import native
+    _say("region map %dx%d" % (spec.nr, spec.nz))
+    p = native.Problem.from_spec(spec)
+    assert np.array_equal(p.region_map(), oracle.Problem.from_spec(spec).region_map())
+
+
+@pytest.mark.parametrize("scheme", ["pr", "lod"])
+@pytest.mark.parametrize("nr,nz", [(7, 12), (5, 9), (13, 31)])
+def test_tiny_all_boundary_classes(scheme, nr, nz):
+    s = tiny_spec(nr=nr, nz=nz, scheme=scheme)
+    _say("tiny %s %dx%d" % (scheme, nr, nz))
+    P, want, _ = run_oracle(s, 7)
+    p, got = run_gpu(s, 7)
+    act = P.active()
+    assert np.all(np.isnan(got[~act]))
+    assert rel_inf(got, want, act) <= TOL
+
+
+@pytest.mark.parametrize("scheme", ["lod", "pr"])
+def test_single_layout_full_run(scheme):
+    """The fixed 64 x 160 instance, dt = 1e-3, 1000 steps, and its 64-point
+    terminal-face profile."""
+    s = W.single_layout(scheme=scheme)
+    _say("single layout %s" % scheme)
+    P, want, _ = run_oracle(s, s.nsteps)
+    p, got = run_gpu(s, s.nsteps)
+    act = P.active()
+    assert rel_inf(got, want, act) <= TOL
+    prof = p.profile(0, 64)
+    wprof = P.profile(want, 0, 64)
+    assert np.max(np.abs(prof - wprof)) <= TOL * np.max(np.abs(wprof))
+    prof1 = p.profile(1, 50)
+    assert np.max(np.abs(prof1 - P.profile(want, 1, 50))) <= TOL * np.max(np.abs(wprof))
+
+
+SHAPES_R = [(4, 16, 1), (8, 16, 1), (12, 8, 2), (8, 4, 1), (12, 4, 1), (16, 4, 1), (8, 2, 1),
+            (16, 2, 1), (8, 1, 1), (16, 1, 1), (8, 1, 2), (8, 2, 2), (20, 8, 4), (20, 4, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_R, ids=lambda s: "m%d_l%d_w%d" % s)
+def test_launch_shapes_ragged(shape):
+    """Every launch shape on a grid whose lines are not multiples of any
+    chunking (ragged tails, chunks that are pure padding) in both
+    directions, both schemes, with several line groups per workgroup."""
+    m, lpw, wpl = shape
+    s = W.production(3, nr=37, nz=91).replace(dt=2e-3)
+    for d, n in ((0, s.nr), (1, s.nz)):
+        G = (64 // lpw) * wpl
+        chunk = max(3, -(-n // G))
+        if chunk > m:
+            continue
+        for scheme in ("pr", "lod"):
+            ss = s.replace(scheme=scheme)
+            _say("shape %s dir %d scheme %s" % (shape, d, scheme))
+            P, want, _ = run_oracle(ss, 5)
+            ngw = max(1, 256 // (64 * wpl))
+            p, got = run_gpu(ss, 5, launch={d: (chunk, lpw, wpl, ngw)})
+            assert rel_inf(got, want, P.active()) <= TOL, (shape, d, scheme)
+
+
+def test_production_full_size_short_run():
+    """1024 x 2560 at the production time step, in the default launch shape
+    of the benchmark: full-field parity after 4 steps (both schemes)."""
+    for scheme in ("pr", "lod"):
+        s = W.production(0, scheme=scheme)
+        _say("production full size %s" % scheme)
+        P, want, _ = run_oracle(s, 4)
+        p, got = run_gpu(s, 4)
+        assert rel_inf(got, want, P.active()) <= TOL
+
+
+def test_production_energy_identity_long_run():
+    """At full size and full length the per-step energy identity is checked
+    on the device every 100 steps; here 2000 steps with checks every 50 and
+    a graph of 50 steps, and the final field is finite and non-negative
+    (Q >= 0, T0 = T_inf = 0: maximum principle holds for the L-stable
+    scheme)."""
+    s = W.production(2, scheme="lod")
+    _say("production energy lod")
+    p, got = run_gpu(s, 2000, graph_steps=50, check_every=50)
+    e = p.energy()
+    assert e["checks"] == 40
+    assert e["residual"] < 1e-11
+    assert np.nanmin(got) >= 0.0
+
+
+def test_graph_and_checks_do_not_change_results():
+    s = W.production(1, nr=200, nz=500)
+    _say("graph vs plain")
+    _, a = run_gpu(s, 120)
+    _, b = run_gpu(s, 120, graph_steps=30, check_every=30)
+    _, c = run_gpu(s, 120, graph_steps=40)
+    act = ~np.isnan(a)
+    assert np.array_equal(a[act], b[act]) and np.array_equal(a[act], c[act])
+
+
+def test_energy_report_matches_oracle():
+    s = tiny_spec(nr=11, nz=17)
+    P, want, _ = run_oracle(s, 9)
+    p, got = run_gpu(s, 9)
+    e = p.energy()
+    o = P.energy(want)
+    assert abs(e["E"] - o["E"]) <= 1e-12 * abs(o["E"])
+    assert abs(e["source_power"] - o["P"]) <= 1e-13 * abs(o["P"])
+    assert abs(e["boundary_flow"] - (o["Br"] + o["Bz"])) <= 1e-11 * (abs(o["Br"]) + abs(o["Bz"]))
+    assert e["steps"] == 9 and abs(e["time"] - 9 * s.dt) < 1e-15
+
+
+def test_nonuniform_layer_aligned_grid():
+    """Face arrays uniform inside each layer (the grid style of Sec. 5),
+    with strongly different cell widths."""
+    r_f = W.layer_aligned_faces((0.0, 2.0, 3.0, 4.0, 4.2), (20, 7, 9, 3))
+    z_f = W.layer_aligned_faces((0.0, 8.0, 10.0, 10.2), (30, 12, 4))
+    s = W.single_layout(nr=39, nz=46, scheme="pr").replace(r_faces=r_f, z_faces=z_f, dt=5e-3)
+    P, want, _ = run_oracle(s, 40)
+    p, got = run_gpu(s, 40)
+    assert rel_inf(got, want, P.active()) <= TOL
+    assert np.array_equal(p.region_map(), P.region_map())
+
+
+def test_set_field_and_continuation():
+    """Stepping 3 + 4 equals stepping 7; a host field is accepted; changing
+    dt rebuilds the tables."""
+    s = tiny_spec(nr=20, nz=33)
+    rng = np.random.default_rng(0)
+    P = oracle.Problem.from_spec(s)
+    T0 = np.where(P.active(), rng.uniform(0, 1, P.shape), 0.0)
+    want, _ = P.step(T0, s.scheme, s.dt, 7)
+    want, _ = P.step(want, s.scheme, 2 * s.dt, 2)
+    from paper_1912_03744_amd import native
+    p = native.Problem.from_spec(s)
+    p.set_field(T0)
+    p.step(s.dt, 3)
+    p.step(s.dt, 4)
+    p.step(2 * s.dt, 2)
+    assert rel_inf(p.read_field(), want, P.active()) <= TOL
+
+
+def test_state_errors():
+    from paper_1912_03744_amd import native
+    s = tiny_spec()
+    p = native.Problem(s.geom, s.nr, s.nz, s.h, s.t_inf)
+    with pytest.raises(native.AdiError) as e:
+        p.step(0.1, 1)
+    assert e.value.status == native.ADI_ESTATE
+    p.set_materials(s.k, s.rhoc)
+    with pytest.raises(native.AdiError):
+        p.set_materials((1, 1, -1, 1, 1), s.rhoc)
+    with pytest.raises(native.AdiError) as e:
+        p.set_sources((0, 0, math.nan, 0, 0))
+    assert e.value.status == native.ADI_ENONFINITE
+    p.set_sources(s.q)
+    with pytest.raises(native.AdiError):
+        p.step(-1.0, 1)
+    p.step(0.1, 1)
+    with pytest.raises(native.AdiError):
+        p.set_launch(0, 2, 4, 1, 1)
