@@ -1,0 +1,171 @@
+"""Benchmark: ADI time stepping of the production-resolution problem on one
+MI355X.
+
+Workload: the layered-cylinder layout at 1024 (r) x 2560 (z) cells, seeded
+materials (seed 0), Peaceman-Rachford steps of dt = 1e-4 with the device
+energy-identity check every 100 steps.  A step is one full ADI step: the
+r-implicit sweep and the z-implicit sweep over the whole grid (and, every 100
+steps, the three energy reductions and the identity check).
+
+Prints one JSON line:
+  value       active-cell updates per second (cells inside the domain x steps
+              / wall time, inputs resident in HBM)
+  roofline    the dominant sweep kernel against MI355X's 8 TB/s HBM peak:
+              algorithmic bytes per launch (16 B per active cell: the
+              right-hand side read once and the next one written once) over
+              its mean launch time, measured with HIP events on the stream
+              the kernel runs on
+  cpu_baseline  the CPU FP64 oracle timed on a bounded sample of the same
+              workload on this host
+Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 200]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_HALF_STEP = 16
+
+
+def source_digest():
+    """Hash of the HIP sources, to tie stored counter readings to a build."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1912_03744_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_counters_production_1024x2560.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(spec, steps):
+    import numpy as np
+
+    import oracle
+    P = oracle.Problem.from_spec(spec)
+    T = P.initial(spec.T0)
+    active = int(np.count_nonzero(P.active()))
+    t0 = time.perf_counter()
+    P.step(T, spec.scheme, spec.dt, steps)
+    dt = time.perf_counter() - t0
+    return {"value": active * steps / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d PR steps of the %dx%d grid from T0 (single-threaded C, -O2)"
+                      % (steps, spec.nr, spec.nz), "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10_000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_03744_amd import native
+    from paper_1912_03744_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    spec = W.production(args.seed)
+    p = native.Problem.from_spec(spec)
+    # launch shapes: the project autotuner (times every compiled shape once,
+    # outside the timed region; cached per GPU architecture and grid)
+    from paper_1912_03744_amd import autotune
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = autotune.apply(p, spec.dt, spec.scheme)
+        print("bench: autotune %.1f s -> r %s z %s" % (time.perf_counter() - t0, tuned["r"]["shape"],
+              tuned["z"]["shape"]), file=sys.stderr, flush=True)
+    p.set_check(100, 1e-9)
+    p.set_graph_steps(args.graph_steps)
+    active = int(np.count_nonzero(p.region_map() != 255))
+    cells = spec.nr * spec.nz
+    print("bench: %dx%d, %d active cells, launch r=%s z=%s" % (spec.nr, spec.nz, active,
+          p.get_launch(0), p.get_launch(1)), file=sys.stderr, flush=True)
+
+    p.step(spec.dt, args.warmup)
+    p.read_field()  # synchronises and surfaces latched errors
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.step(spec.dt, args.steps)
+    torch.cuda.synchronize()
+    p.energy()  # raises if a periodic check failed
+    wall = time.perf_counter() - t0
+    rep = p.energy()
+    T = p.read_field()
+    assert np.all(np.isfinite(T[~np.isnan(T)]))
+    print("bench: %d steps in %.4f s, energy residual %.2e over %d checks"
+          % (args.steps, wall, rep["residual"], rep["checks"]), file=sys.stderr, flush=True)
+
+    # dominant kernel: mean launch time of each sweep, HIP events on its stream
+    ms_r, ms_z = p.time_sweeps(spec.dt, 200)
+    kern, ms = ("sweep_z", ms_z) if ms_z >= ms_r else ("sweep_r", ms_r)
+    alg_bytes = BYTES_PER_CELL_HALF_STEP * active
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    traffic = stored_traffic(kern)
+
+    out = {
+        "metric": "cell-updates/s per ADI step",
+        "value": active * args.steps / wall,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "layered cylinder %dx%d, seeded materials (seed %d), %s, dt=%g, "
+                               "%d steps, energy check every 100 steps"
+                               % (spec.nr, spec.nz, args.seed, "Peaceman-Rachford", spec.dt, args.steps),
+                   "active_cells": active, "cells": cells, "graph_steps": args.graph_steps,
+                   "launch_r": list(p.get_launch(0)), "launch_z": list(p.get_launch(1))},
+        "roofline": {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "ms_per_launch": {"sweep_r": ms_r, "sweep_z": ms_z},
+                     "alg_bytes_per_launch": alg_bytes},
+        "cups_all_cells": cells * args.steps / wall,
+        "energy_residual": rep["residual"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -153,16 +153,21 @@ adi_status adi_energy(adi_problem p, adi_energy_report* out);
 adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_r, float* ms_z);
 
 /* Launch shape of the line solves (advanced; the autotuner uses it).
- * dir 0 = r lines, 1 = z lines.  chunk: cells per lane (3..48);
- * lines_per_wave: 1, 2, 4, 8 or 16 (lanes of a wave split into this many
- * lines); waves_per_line: 1, 2, 4, 8 or 16; groups_per_block: line groups
- * per workgroup (1..16, at most 1024 threads).  The chunk count
- * (64/lines_per_wave)*waves_per_line times chunk must cover the line length.
- * ADI_EUNSUPPORTED if this build has no kernel for the shape. */
+ * dir 0 = r lines, 1 = z lines.  chunk: cells per lane and line; a wave's
+ * lanes form lines_per_wave slots x (64/lines_per_wave) chunks; a line spans
+ * waves_per_line waves; each lane handles lines_per_lane lines; a workgroup
+ * runs groups_per_block line groups.  (64/lines_per_wave)*waves_per_line*chunk
+ * must cover the line length.  Only compiled shapes are accepted
+ * (ADI_EUNSUPPORTED otherwise); see adi_launch_shapes. */
 adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lines_per_wave,
-                          int32_t waves_per_line, int32_t groups_per_block);
+                          int32_t waves_per_line, int32_t lines_per_lane, int32_t groups_per_block);
 adi_status adi_get_launch(adi_problem p, int32_t dir, int32_t* chunk, int32_t* lines_per_wave,
-                          int32_t* waves_per_line, int32_t* groups_per_block);
+                          int32_t* waves_per_line, int32_t* lines_per_lane, int32_t* groups_per_block);
+
+/* Launch shapes compiled into this build: writes up to max_shapes records
+ * (chunk, lines_per_wave, waves_per_line, lines_per_lane, groups_per_block)
+ * to out (5*max_shapes int32) and the number of shapes to *count. */
+adi_status adi_launch_shapes(int32_t* out, int32_t max_shapes, int32_t* count);
 
 /* Steps per captured HIP graph in adi_step (0 = plain launches). */
 adi_status adi_set_graph_steps(adi_problem p, int32_t steps);

@@ -1,0 +1,108 @@
+"""Launch-shape autotuner for the line-solve sweeps.
+
+For each sweep direction of a problem it times every compiled launch shape
+(cells per chunk, lines per wave, waves per line, lines per lane, groups per
+workgroup) that covers the line length without too much padding, using
+adi_time_sweeps (HIP events on the problem's stream), and keeps the fastest.  Results are cached in a
+JSON file keyed by GPU architecture, grid size and scheme: $ADI_AUTOTUNE_CACHE
+or ~/.cache/adi_autotune.json.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import native
+
+CACHE_ENV = "ADI_AUTOTUNE_CACHE"
+
+
+def cache_path():
+    return os.environ.get(CACHE_ENV) or os.path.join(os.path.expanduser("~"), ".cache",
+                                                    "adi_autotune.json")
+
+
+def _arch():
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def key(nr, nz, scheme):
+    return "%s/%dx%d/%s" % (_arch(), nr, nz, scheme)
+
+
+def candidates(n, nlines, max_pad=2.0):
+    """Compiled shapes (chunk, lines_per_wave, waves_per_line, lines_per_lane,
+    groups_per_block) covering a line of n cells with at most max_pad
+    padding."""
+    out = []
+    for m, lpw, wpl, r, ngw in native.launch_shapes():
+        G = (64 // lpw) * wpl
+        if G * m < n or G * m > max_pad * max(n, 16):
+            continue
+        if lpw * r > max(1, nlines):
+            continue
+        out.append((m, lpw, wpl, r, ngw))
+    return out
+
+
+def tune(problem, dt, nlaunch=20, reps=2, verbose=False, log=None):
+    """Time every candidate shape in both directions and set the fastest.
+    Returns {"r": (shape, ms), "z": (shape, ms), "trials": [...]}."""
+    res = {"trials": []}
+    dims = {0: (problem.nr, problem.nz), 1: (problem.nz, problem.nr)}
+    for d in (0, 1):
+        n, nlines = dims[d]
+        best = None
+        for shape in candidates(n, nlines):
+            problem.set_launch(d, *shape)
+            t = min(problem.time_sweeps(dt, nlaunch)[d] for _ in range(reps))
+            res["trials"].append({"dir": d, "shape": shape, "ms": t})
+            if verbose:
+                msg = "autotune dir %d shape %s: %.4f ms" % (d, shape, t)
+                print(msg, flush=True) if log is None else log(msg)
+            if best is None or t < best[1]:
+                best = (shape, t)
+        problem.set_launch(d, *best[0])
+        res["rz"[d]] = best
+    return res
+
+
+def apply(problem, dt, scheme, retune=False, verbose=False, log=None):
+    """Set the cached best shapes for this problem size, tuning on a miss."""
+    db = _load()
+    k = key(problem.nr, problem.nz, scheme)
+    if not retune and k in db:
+        for d, name in ((0, "r"), (1, "z")):
+            problem.set_launch(d, *db[k][name]["shape"])
+        return db[k]
+    t0 = time.time()
+    r = tune(problem, dt, verbose=verbose, log=log)
+    entry = {"r": {"shape": list(r["r"][0]), "ms": r["r"][1]},
+             "z": {"shape": list(r["z"][0]), "ms": r["z"][1]},
+             "seconds": time.time() - t0, "trials": len(r["trials"])}
+    db = _load()
+    db[k] = entry
+    _store(db)
+    return entry

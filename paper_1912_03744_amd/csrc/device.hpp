@@ -37,6 +37,17 @@ namespace adi {
 
 constexpr uint8_t MASKED = 255;
 
+// Keep the scheduler from hoisting the factor-table loads of later steps of
+// an unrolled recurrence (which would exhaust registers); loads of the
+// current step still overlap with the arithmetic of the previous one.
+#define ADI_STEP_FENCE()                                  \
+  do {                                                    \
+    if constexpr (M * R > ADI_FENCE_CELLS) __builtin_amdgcn_sched_barrier(0); \
+  } while (0)
+#ifndef ADI_FENCE_CELLS
+#define ADI_FENCE_CELLS 12  // short chunks keep all their table loads in flight
+#endif
+
 // ------------------------------------------------------------ descriptors --
 
 // Problem parameters of one instance as the device sees them.
@@ -73,20 +84,14 @@ enum PosField {
   P_NFIELDS
 };
 
-constexpr int MAX_LEV = 6;  // log2(64): chunks per wave
-
-// Per-chunk fields.
+// Per-chunk fields: the chunk's two rows of the reduced system.
 enum ChkField {
   C_CS = 0,  // super-diagonal of the chunk's first row
   C_AE,      // sub-diagonal of the chunk's last row
   C_W0, C_Q0, C_C0,   // reduced-system Thomas factors of row 2k
   C_W1, C_Q1, C_C1,   // ... of row 2k+1
-  C_CPREV,   // C of row 2k-1
-  C_BPRE,    // prefix product of the forward coefficients within the wave
-  C_ESUF,    // suffix product of the backward coefficients within the wave
-  C_KSF,     // MAX_LEV forward doubling coefficients
-  C_KSB = C_KSF + MAX_LEV,  // MAX_LEV backward doubling coefficients
-  C_NFIELDS = C_KSB + MAX_LEV
+  C_CPREV,   // C of row 2k-1 (the previous chunk's last row)
+  C_NFIELDS
 };
 
 // One line class in one direction.
@@ -97,17 +102,22 @@ struct LineTab {
   int skip_lo, skip_hi;  // positions [skip_lo, skip_hi) are outside the domain
 };
 
-// Arguments of one sweep (one direction of one instance).
+constexpr int MAX_CLS = 4;
+
+// Arguments of one sweep (one direction of one instance).  The lines of a
+// class form one contiguous index range [cls_l0[c], cls_l1[c]); line groups
+// never straddle two classes, so every group reads one set of tables: class c
+// owns groups [cls_g0[c], cls_g0[c+1]).
 struct SweepArgs {
   const double* din;      // right-hand side of this half step
   double* dout;           // right-hand side of the next half step
   double* xout;           // solution of this half step, or null
   const LineTab* tabs;    // line-class tables of this direction
-  const uint8_t* line_class;  // class of every line
   const uint8_t* pos_xclass;  // class of the crossing line at every position
   const double* xc;       // [xclass][line] constant of the other direction, or null
   long line_stride, pos_stride;
-  int nlines, ngroups;
+  int nlines, ncls, ngroups;
+  int cls_l0[MAX_CLS], cls_l1[MAX_CLS], cls_g0[MAX_CLS + 1];
 };
 
 // ---------------------------------------------------------------- regions --
@@ -147,9 +157,12 @@ __device__ __forceinline__ void axis_point(int i, int n, double length, const do
   d[i] = f1 - f0;
 }
 
-// Fill the geometry arrays; called by one workgroup (any size).
+// Fill the geometry arrays; called by one workgroup (any size).  ranges
+// receives, per direction (0: rows by band, 1: columns by class) and class,
+// the index range [first, last+1) of its lines; ranges[16] is set to 1 if a
+// class is not one contiguous range (centres are monotone, so never).
 __device__ void build_geometry(const Params& P, const double* rfaces_in, const double* zfaces_in,
-                               const Geom& g) {
+                               const Geom& g, int* ranges) {
   for (int i = threadIdx.x; i < P.nr; i += blockDim.x) {
     axis_point(i, P.nr, P.rmax, rfaces_in, g.rf, g.rc, g.dr);
     g.kap[i] = (uint8_t)column_class(P, g.rc[i]);
@@ -157,6 +170,28 @@ __device__ void build_geometry(const Params& P, const double* rfaces_in, const d
   for (int j = threadIdx.x; j < P.nz; j += blockDim.x) {
     axis_point(j, P.nz, P.ztop, zfaces_in, g.zf, g.zc, g.dz);
     g.bet[j] = (uint8_t)row_band(P, g.zc[j]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    for (int dir = 0; dir < 2; ++dir) {
+      const uint8_t* cl = dir == 0 ? g.bet : g.kap;
+      const int n = dir == 0 ? P.nz : P.nr;
+      for (int c = 0; c < MAX_CLS; ++c) {
+        int lo = -1, hi = -1, cnt = 0;
+        for (int q = 0; q < n; ++q)
+          if (cl[q] == c) {
+            if (lo < 0) lo = q;
+            hi = q + 1;
+            ++cnt;
+          }
+        if (cnt == 0) lo = hi = 0;
+        if (cnt != hi - lo) bad = 1;
+        ranges[(dir * MAX_CLS + c) * 2] = lo;
+        ranges[(dir * MAX_CLS + c) * 2 + 1] = hi;
+      }
+    }
+    ranges[16] = bad;
   }
 }
 
@@ -264,8 +299,7 @@ __host__ __device__ constexpr long assemble_work(int G, int M) { return 3L * G *
 //  weights, xc: [n] boundary constants of this direction (the other
 //  direction's sweeps add them), work: assemble_work(G, M) doubles.
 __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls, int G, int M,
-                               int CPW, double* pos, double* chk, double* eng, double* xc,
-                               double* work) {
+                               double* pos, double* chk, double* eng, double* xc, double* work) {
   const int n = dir == 0 ? P.nr : P.nz;
   const int GM = G * M;
   double* A = work;
@@ -352,7 +386,7 @@ __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls,
   }
   __syncthreads();
 
-  // Phase 4: per-chunk factors and the products used by recursive doubling.
+  // Phase 4: per-chunk factors of the reduced system.
   for (int k = threadIdx.x; k < G; k += blockDim.x) {
     chk[C_W0 * G + k] = rW[2 * k];
     chk[C_Q0 * G + k] = rQ[2 * k];
@@ -361,181 +395,278 @@ __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls,
     chk[C_Q1 * G + k] = rQ[2 * k + 1];
     chk[C_C1 * G + k] = rC[2 * k + 1];
     chk[C_CPREV * G + k] = k > 0 ? rC[2 * k - 1] : 0.0;
-    auto Bf = [&](int t) { return rQ[2 * t + 1] * rQ[2 * t]; };
-    auto Eb = [&](int t) { return rC[2 * t] * rC[2 * t + 1]; };
-    const int ws = (k / CPW) * CPW, we = ws + CPW - 1;
-    double pre = 1.0;
-    for (int t = ws; t <= k; ++t) pre *= Bf(t);
-    double suf = 1.0;
-    for (int t = k; t <= we; ++t) suf *= Eb(t);
-    chk[C_BPRE * G + k] = pre;
-    chk[C_ESUF * G + k] = suf;
-    for (int lev = 0; lev < MAX_LEV; ++lev) {
-      const int d = 1 << lev;
-      double f = 0.0, b = 0.0;
-      if (k - d >= ws) {
-        f = 1.0;
-        for (int t = k - d + 1; t <= k; ++t) f *= Bf(t);
-      }
-      if (k + d <= we) {
-        b = 1.0;
-        for (int t = k; t <= k + d - 1; ++t) b *= Eb(t);
-      }
-      chk[(C_KSF + lev) * G + k] = f;
-      chk[(C_KSB + lev) * G + k] = b;
-    }
   }
   __syncthreads();
 }
 
 // ------------------------------------------------------------ line solve --
 
-// Solve the lines of one line group: LPW lines side by side in each wave,
-// each line spread over CPW = 64/LPW chunks per wave and WPL waves.  `lds`
-// holds LPW*WPL doubles for this group.  `valid` is false for groups past the
-// end (they still take part in the barriers).
-template <int MM, int LPW, int WPL>
+// Bit t set iff position p0 + t of a chunk is a real cell (below n) outside
+// the skipped run [skip_lo, skip_hi).
+__device__ __forceinline__ unsigned long long chunk_live_mask(int p0, int M, int n, int skip_lo,
+                                                              int skip_hi) {
+  auto below = [](int c) -> unsigned long long {  // bits [0, c)
+    return c <= 0 ? 0ull : (c >= 64 ? ~0ull : ((1ull << c) - 1ull));
+  };
+  const int m = M < n - p0 ? M : n - p0;
+  return below(m) & ~(below(skip_hi - p0) & ~below(skip_lo - p0));
+}
+
+// Solve one line group.  The group has LPW lane slots per wave, each slot
+// owning R consecutive lines; every line is spread over CPW = 64/LPW chunks
+// per wave and WPL waves, M cells per chunk.  A lane therefore holds an
+// R x M block: the same chunk of R lines, so each factor-table value it
+// loads serves R lines.  All sizes are compile-time, so every loop unrolls
+// without branches.  The reduced system is solved by recursive doubling on
+// affine maps (x_k = A + B x_{k-2^s}): (A, B) pairs are combined through
+// wave shuffles, with a carry through LDS when a line spans several waves.
+// `lds` holds WPL*LPW*(R+1) doubles for this group; groups past the end
+// (valid = false) still take part in the barriers.
+// CONTIG: positions of a line are adjacent in memory (pos_stride == 1, r
+// lines); the chunk is then moved with 16-byte accesses where it lies inside
+// the line.  Otherwise lines are adjacent (line_stride == 1, z lines).
+template <int M, int LPW, int WPL, int R, bool CONTIG>
 __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, double* lds, bool valid,
-                                            int wave_in_group) {
+                                            int wv) {
+  static_assert(M >= 3, "chunks need an interior row");
   constexpr int CPW = 64 / LPW;
+  constexpr int G = CPW * WPL;
+  constexpr int GM = G * M;
   constexpr int LEV = __builtin_ctz(CPW);
   const int lane = threadIdx.x & 63;
   const int li = lane % LPW;
   const int ci = lane / LPW;
-  const int wv = wave_in_group;
   const int k = wv * CPW + ci;
-  const int L = group * LPW + li;
-  const bool act = valid && L < a.nlines;
-  const int cls = act ? a.line_class[L] : a.line_class[0];
-  const LineTab tb = a.tabs[cls];
-  const int M = tb.M, G = tb.G, GM = G * M;
-  const double* __restrict__ pos = tb.pos;
-  const double* __restrict__ chk = tb.chk;
-  const long base = (long)(act ? L : 0) * a.line_stride;
 
-  double v[MM];
+  // class of the group (uniform across the group)
+  int c = 0;
+  while (c + 1 < a.ncls && group >= a.cls_g0[c + 1]) ++c;
+  const int Lfirst = a.cls_l0[c] + (group - a.cls_g0[c]) * (LPW * R) + li * R;
+  const int Lend = valid ? a.cls_l1[c] : 0;
+  const LineTab tb = a.tabs[c];
+  const double* __restrict__ pos = tb.pos + k;
+  const double* __restrict__ chk = tb.chk + k;
+  const int p0 = k * M;
+
+  // Addresses: a uniform base (scalar registers) plus one 32-bit byte offset
+  // per lane; the per-step and per-line increments are uniform too.
+  const long ls8 = a.line_stride * 8, ps8 = a.pos_stride * 8;
+  const unsigned lane_off = (unsigned)((long)Lfirst * ls8 + (long)p0 * ps8);
+  const char* __restrict__ din = (const char*)a.din;
+  // bit t set: chunk offset t is a real cell inside the domain
+  const unsigned long long live = chunk_live_mask(p0, M, tb.n, tb.skip_lo, tb.skip_hi);
+  // cells of the chunk that lie inside the line (readable even if masked)
+  const int inl = tb.n - p0;
+  const bool pairs_ok = CONTIG && (M % 2 == 0) && ((a.line_stride & 1) == 0);
+
+  double v[R][M];
 #pragma unroll
-  for (int t = 0; t < MM; ++t) {
-    v[t] = 0.0;
-    if (t < M) {
-      const int p = k * M + t;
-      const bool ok = act && p < tb.n && (p < tb.skip_lo || p >= tb.skip_hi);
-      if (ok) v[t] = a.din[base + (long)p * a.pos_stride];
+  for (int r = 0; r < R; ++r) {
+    const bool act = Lfirst + r < Lend;
+    const char* rowp = din + (long)r * ls8;  // uniform
+    if (pairs_ok) {
+#pragma unroll
+      for (int t = 0; t < M; t += 2) {
+        double2 q = make_double2(0.0, 0.0);
+        if (act && t + 1 < inl) q = *(const double2*)(rowp + lane_off + t * 8);
+        else if (act && t < inl) q.x = *(const double*)(rowp + lane_off + t * 8);
+        v[r][t] = ((live >> t) & 1ull) ? q.x : 0.0;
+        v[r][t + 1] = ((live >> (t + 1)) & 1ull) ? q.y : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        const bool ok = act && ((live >> t) & 1ull);
+        v[r][t] = ok ? *(const double*)(rowp + (long)t * ps8 + lane_off) : 0.0;
+      }
     }
   }
-  const double ds = v[0];
-  double de = 0.0;
-#pragma unroll
-  for (int t = 0; t < MM; ++t)
-    if (t == M - 1) de = v[t];
 
   // interior forward elimination and back substitution (rows 1..M-2)
-  double run = 0.0;
+  double run[R];
 #pragma unroll
-  for (int t = 1; t < MM - 1; ++t) {
-    if (t <= M - 2) {
-      const int ix = t * G + k;
-      run = v[t] * pos[P_W * GM + ix] - pos[P_QA * GM + ix] * run;
-      v[t] = run;
+  for (int r = 0; r < R; ++r) run[r] = 0.0;
+#pragma unroll
+  for (int t = 1; t <= M - 2; ++t) {
+    ADI_STEP_FENCE();
+    const double w = pos[P_W * GM + t * G], qa = pos[P_QA * GM + t * G];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      run[r] = v[r][t] * w - qa * run[r];
+      v[r][t] = run[r];
     }
   }
-  run = 0.0;
 #pragma unroll
-  for (int t = MM - 2; t >= 1; --t) {
-    if (t <= M - 2) {
-      run = v[t] - pos[P_CP * GM + t * G + k] * run;
-      v[t] = run;
+  for (int r = 0; r < R; ++r) run[r] = 0.0;
+#pragma unroll
+  for (int t = M - 2; t >= 1; --t) {
+    ADI_STEP_FENCE();
+    const double cp = pos[P_CP * GM + t * G];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      run[r] = v[r][t] - cp * run[r];
+      v[r][t] = run[r];
     }
   }
-  double zl = 0.0;
-#pragma unroll
-  for (int t = 1; t < MM; ++t)
-    if (t == M - 2) zl = v[t];
-  const double g0 = ds - chk[C_CS * G + k] * v[1 < MM ? 1 : 0];
-  const double g1 = de - chk[C_AE * G + k] * zl;
 
-  // reduced system, forward recurrence F_k = A_k + B_k F_{k-1}
-  const double W0 = chk[C_W0 * G + k], Q0 = chk[C_Q0 * G + k], C0 = chk[C_C0 * G + k];
-  const double W1 = chk[C_W1 * G + k], Q1 = chk[C_Q1 * G + k], C1 = chk[C_C1 * G + k];
-  const double g0w = g0 * W0;
-  double F = g1 * W1 - Q1 * g0w;
+  // reduced system: forward recurrence F_k = A_k + B_k F_{k-1}
+  const double cs = chk[C_CS * G], ae = chk[C_AE * G];
+  const double W0 = chk[C_W0 * G], Q0 = chk[C_Q0 * G], C0 = chk[C_C0 * G];
+  const double W1 = chk[C_W1 * G], Q1 = chk[C_Q1 * G], C1 = chk[C_C1 * G];
+  const double cprev = chk[C_CPREV * G];
+  double g0w[R], F[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    g0w[r] = (v[r][0] - cs * v[r][1]) * W0;
+    F[r] = (v[r][M - 1] - ae * v[r][M - 2]) * W1 - Q1 * g0w[r];
+  }
+  double B = Q1 * Q0;
 #pragma unroll
   for (int lev = 0; lev < LEV; ++lev) {
     const int d = 1 << lev;
-    const double o = __shfl_up(F, d * LPW, 64);
-    if (ci >= d) F += chk[(C_KSF + lev) * G + k] * o;
+    const double Bo = __shfl_up(B, d * LPW, 64);
+    double Ao[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Ao[r] = __shfl_up(F[r], d * LPW, 64);
+    if (ci >= d) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) F[r] += B * Ao[r];
+      B *= Bo;
+    }
   }
-  double Fin = 0.0;
+  double Fin[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) Fin[r] = 0.0;
   if constexpr (WPL > 1) {
-    if (ci == CPW - 1) lds[li * WPL + wv] = F;
+    double* slot = lds + (wv * LPW + li) * (R + 1);
+    if (ci == CPW - 1) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) slot[r] = F[r];
+      slot[R] = B;
+    }
     __syncthreads();
-    double cin = 0.0;
-    for (int w = 0; w < wv; ++w) cin = lds[li * WPL + w] + chk[C_BPRE * G + w * CPW + CPW - 1] * cin;
-    F += chk[C_BPRE * G + k] * cin;
-    Fin = cin;
+    for (int w = 0; w < wv; ++w) {
+      const double* o = lds + (w * LPW + li) * (R + 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) Fin[r] = o[r] + o[R] * Fin[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] += B * Fin[r];
     __syncthreads();
   }
-  double Fprev = __shfl_up(F, LPW, 64);
-  if (ci == 0) Fprev = Fin;
+  double Fprev[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    Fprev[r] = __shfl_up(F[r], LPW, 64);
+    if (ci == 0) Fprev[r] = Fin[r];
+  }
 
   // backward recurrence U_k = H_k + E_k U_{k+1}
-  const double f0 = g0w - Q0 * Fprev;
-  double U = f0 - C0 * F;
+  double U[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) U[r] = g0w[r] - Q0 * Fprev[r] - C0 * F[r];
+  double E = C0 * C1;
 #pragma unroll
   for (int lev = 0; lev < LEV; ++lev) {
     const int d = 1 << lev;
-    const double o = __shfl_down(U, d * LPW, 64);
-    if (ci + d < CPW) U += chk[(C_KSB + lev) * G + k] * o;
-  }
-  double Uin = 0.0;
-  if constexpr (WPL > 1) {
-    if (ci == 0) lds[li * WPL + wv] = U;
-    __syncthreads();
-    double cin = 0.0;
-    for (int w = WPL - 1; w > wv; --w) cin = lds[li * WPL + w] + chk[C_ESUF * G + w * CPW] * cin;
-    U += chk[C_ESUF * G + k] * cin;
-    Uin = cin;
-    __syncthreads();
-  }
-  double Unext = __shfl_down(U, LPW, 64);
-  if (ci == CPW - 1) Unext = Uin;
-
-  const double xs = U;                                   // first unknown of the chunk
-  const double xe = F - C1 * Unext;                      // last unknown
-  const double xm1 = Fprev - chk[C_CPREV * G + k] * U;   // last unknown of chunk k-1
-  const double xp1 = Unext;                              // first unknown of chunk k+1
-
-  // interior back substitution
-  v[0] = xs;
+    const double Eo = __shfl_down(E, d * LPW, 64);
+    double Uo[R];
 #pragma unroll
-  for (int t = 1; t < MM; ++t) {
-    if (t <= M - 2) {
-      const int ix = t * G + k;
-      v[t] = v[t] - pos[P_SP * GM + ix] * xs - pos[P_SR * GM + ix] * xe;
-    } else if (t == M - 1) {
-      v[t] = xe;
+    for (int r = 0; r < R; ++r) Uo[r] = __shfl_down(U[r], d * LPW, 64);
+    if (ci + d < CPW) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) U[r] += E * Uo[r];
+      E *= Eo;
     }
   }
-
-  // outputs: solution (optional) and the next half step's right-hand side
-  double xprev = xm1;
+  double Uin[R];
 #pragma unroll
-  for (int t = 0; t < MM; ++t) {
-    if (t < M) {
-      const int p = k * M + t;
-      const bool ok = act && p < tb.n && (p < tb.skip_lo || p >= tb.skip_hi);
-      const double xt = v[t];
-      const double xn = (t + 1 < MM && t + 1 < M) ? v[t + 1 < MM ? t + 1 : t] : xp1;
-      const int ix = t * G + k;
-      double o = pos[P_OD * GM + ix] * xt + pos[P_OL * GM + ix] * xprev +
-                 pos[P_OU * GM + ix] * xn + pos[P_OC * GM + ix];
-      if (ok) {
-        const long addr = base + (long)p * a.pos_stride;
-        if (a.xc) o += a.xc[(long)a.pos_xclass[p] * a.nlines + L];
-        a.dout[addr] = o;
-        if (a.xout) a.xout[addr] = xt;
+  for (int r = 0; r < R; ++r) Uin[r] = 0.0;
+  if constexpr (WPL > 1) {
+    double* slot = lds + (wv * LPW + li) * (R + 1);
+    if (ci == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) slot[r] = U[r];
+      slot[R] = E;
+    }
+    __syncthreads();
+    for (int w = WPL - 1; w > wv; --w) {
+      const double* o = lds + (w * LPW + li) * (R + 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) Uin[r] = o[r] + o[R] * Uin[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) U[r] += E * Uin[r];
+    __syncthreads();
+  }
+
+  // chunk ends and their outer neighbours; interior back substitution
+  double xm1[R], xp1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double un = __shfl_down(U[r], LPW, 64);
+    if (ci == CPW - 1) un = Uin[r];
+    const double xs = U[r];
+    const double xe = F[r] - C1 * un;
+    xm1[r] = Fprev[r] - cprev * U[r];
+    xp1[r] = un;
+    v[r][0] = xs;
+    v[r][M - 1] = xe;
+    F[r] = xs;
+    U[r] = xe;
+  }
+#pragma unroll
+  for (int t = 1; t <= M - 2; ++t) {
+    ADI_STEP_FENCE();
+    const double sp = pos[P_SP * GM + t * G], sr = pos[P_SR * GM + t * G];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r][t] = v[r][t] - sp * F[r] - sr * U[r];
+  }
+
+  // outputs: the next half step's right-hand side (and the solution)
+  double o[R][M];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    ADI_STEP_FENCE();
+    const double od = pos[P_OD * GM + t * G], ol = pos[P_OL * GM + t * G];
+    const double ou = pos[P_OU * GM + t * G], oc = pos[P_OC * GM + t * G];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double xl = t > 0 ? v[r][t > 0 ? t - 1 : 0] : xm1[r];
+      const double xr = t < M - 1 ? v[r][t < M - 1 ? t + 1 : t] : xp1[r];
+      o[r][t] = od * v[r][t] + ol * xl + ou * xr + oc;
+      if (a.xc && ((live >> t) & 1ull) && Lfirst + r < Lend)
+        o[r][t] += a.xc[(long)a.pos_xclass[p0 + t] * a.nlines + Lfirst + r];
+    }
+  }
+  char* __restrict__ dout = (char*)a.dout;
+  char* __restrict__ xout = (char*)a.xout;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool act = Lfirst + r < Lend;
+    const long roff = (long)r * ls8;  // uniform
+    if (pairs_ok) {
+      // cells outside the domain hold 0 in every buffer and come out as 0,
+      // so whole pairs inside the line can be stored
+#pragma unroll
+      for (int t = 0; t < M; t += 2) {
+        if (act && t + 1 < inl) {
+          *(double2*)(dout + roff + lane_off + t * 8) = make_double2(o[r][t], o[r][t + 1]);
+          if (xout) *(double2*)(xout + roff + lane_off + t * 8) = make_double2(v[r][t], v[r][t + 1]);
+        } else if (act && t < inl && ((live >> t) & 1ull)) {
+          *(double*)(dout + roff + lane_off + t * 8) = o[r][t];
+          if (xout) *(double*)(xout + roff + lane_off + t * 8) = v[r][t];
+        }
       }
-      xprev = xt;
+    } else {
+#pragma unroll
+      for (int t = 0; t < M; ++t) {
+        if (act && ((live >> t) & 1ull)) {
+          const long uoff = roff + (long)t * ps8;
+          *(double*)(dout + uoff + lane_off) = o[r][t];
+          if (xout) *(double*)(xout + uoff + lane_off) = v[r][t];
+        }
+      }
     }
   }
 }

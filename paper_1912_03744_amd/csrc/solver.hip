@@ -53,15 +53,15 @@ void dev_free(void* p) {
 
 // ------------------------------------------------------------ kernels ----
 
-__global__ void k_geometry(Params P, const double* rfi, const double* zfi, Geom g) {
-  build_geometry(P, rfi, zfi, g);
+__global__ void k_geometry(Params P, const double* rfi, const double* zfi, Geom g, int* ranges) {
+  build_geometry(P, rfi, zfi, g, ranges);
 }
 
 // Tables of one direction.
 struct DirTabs {
   LineTab* tabs;
   double *pos, *chk, *eng, *xc, *work;
-  int ncls, n, G, M, CPW;
+  int ncls, n, G, M;
 };
 
 // One workgroup per line class: r bands first, then z column classes.
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) k_assemble(Params P, Geom g, DirTabs r, D
   double* eng = D.eng + (long)cls * 2 * D.n;
   double* xc = D.xc + (long)cls * D.n;
   double* work = D.work + cls * assemble_work(D.G, D.M);
-  assemble_class(P, g, dir, cls, D.G, D.M, D.CPW, pos, chk, eng, xc, work);
+  assemble_class(P, g, dir, cls, D.G, D.M, pos, chk, eng, xc, work);
   if (threadIdx.x == 0) {
     // cells outside the domain form one contiguous run of a line
     int lo = D.n, hi = D.n, cnt = 0;
@@ -120,16 +120,31 @@ __global__ void k_init_rhs(const double* __restrict__ T, double* __restrict__ d,
   }
 }
 
-template <int MM, int LPW, int WPL>
-__global__ void __launch_bounds__(1024) k_sweep(SweepArgs a, int ngw) {
-  extern __shared__ double lds[];
+// Workgroups are dealt to the 8 XCDs round-robin by block index; remap so
+// that each XCD gets one contiguous range of line groups, which keeps
+// neighbouring lines (sharing cache lines in the strided direction) in one
+// L2.  A bijection on [0, nblocks).
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  constexpr int NX = 8;
+  const int q = nblocks / NX, rem = nblocks % NX;
+  const int x = b % NX, slot = b / NX;
+  return x * q + (x < rem ? x : rem) + slot;
+}
+
+// NGW line groups per workgroup, WPL waves per group.  The grid has one
+// workgroup per NGW line groups.  Lines along contiguous memory (r) and
+// across it (z) are separate instantiations.
+template <int M, int LPW, int WPL, int R, int NGW>
+__global__ void __launch_bounds__(64 * WPL * NGW) k_sweep(SweepArgs a) {
+  __shared__ double lds[NGW][WPL > 1 ? WPL * LPW * (R + 1) : 1];
   const int wave = threadIdx.x >> 6;
   const int gw = wave / WPL;
   const int wv = wave % WPL;
-  for (int base = blockIdx.x * ngw; base < a.ngroups; base += gridDim.x * ngw) {
-    const int group = base + gw;
-    solve_group<MM, LPW, WPL>(a, group, lds + gw * LPW * WPL, group < a.ngroups, wv);
-  }
+  const int group = xcd_block(blockIdx.x, gridDim.x) * NGW + gw;
+  if (a.pos_stride == 1)
+    solve_group<M, LPW, WPL, R, true>(a, group, lds[gw], group < a.ngroups, wv);
+  else
+    solve_group<M, LPW, WPL, R, false>(a, group, lds[gw], group < a.ngroups, wv);
 }
 
 // Energy and boundary flows of a field, one workgroup per row, fixed-order
@@ -251,35 +266,43 @@ __global__ void k_clear(double* p, int n) {
 
 // ------------------------------------------------------- sweep variants ----
 
-using SweepFn = void (*)(SweepArgs, int);
+using SweepFn = void (*)(SweepArgs);
 struct Variant {
-  int MM, LPW, WPL;
+  int M, LPW, WPL, R, NGW;
   SweepFn fn;
 };
 
-#define ADI_V(mm, lpw, wpl) {mm, lpw, wpl, k_sweep<mm, lpw, wpl>}
+// Compiled launch shapes: cells per chunk M, lines per wave slot group LPW
+// (lanes split into LPW slots x 64/LPW chunks), waves per line WPL, lines
+// per lane R, line groups per workgroup NGW.  A line of n cells runs on any
+// shape with (64/LPW)*WPL*M >= n.
+#define ADI_V(m, lpw, wpl, r, ngw) {m, lpw, wpl, r, ngw, k_sweep<m, lpw, wpl, r, ngw>}
 static const Variant kVariants[] = {
-    // lines mostly along contiguous memory (r): few lines per wave
-    ADI_V(4, 4, 1), ADI_V(8, 4, 1), ADI_V(12, 4, 1), ADI_V(16, 4, 1),
-    ADI_V(8, 2, 1), ADI_V(16, 2, 1), ADI_V(32, 2, 1),
-    ADI_V(8, 1, 1), ADI_V(16, 1, 1), ADI_V(32, 1, 1), ADI_V(8, 1, 2), ADI_V(16, 1, 2),
-    ADI_V(8, 2, 2), ADI_V(16, 2, 2),
-    // strided lines (z): many adjacent lines per wave
-    ADI_V(4, 16, 1), ADI_V(8, 16, 1), ADI_V(12, 16, 2), ADI_V(16, 16, 4), ADI_V(24, 16, 8),
-    ADI_V(20, 16, 16), ADI_V(40, 16, 16), ADI_V(48, 16, 16),
-    ADI_V(12, 8, 2), ADI_V(20, 8, 4), ADI_V(40, 8, 8), ADI_V(20, 8, 16),
-    ADI_V(40, 4, 4), ADI_V(20, 4, 8),
+    // contiguous lines (r)
+    ADI_V(4, 1, 4, 2, 1), ADI_V(4, 1, 4, 4, 1), ADI_V(4, 1, 4, 8, 1), ADI_V(8, 1, 2, 4, 1),
+    ADI_V(8, 1, 2, 8, 1), ADI_V(16, 1, 1, 2, 4), ADI_V(4, 2, 4, 4, 1), ADI_V(8, 1, 2, 2, 2),
+    // strided lines (z)
+    ADI_V(10, 4, 16, 1, 1), ADI_V(10, 4, 16, 2, 1), ADI_V(5, 2, 16, 4, 1), ADI_V(5, 2, 16, 2, 1),
+    ADI_V(5, 1, 8, 8, 1), ADI_V(5, 1, 8, 4, 1), ADI_V(10, 1, 4, 4, 1), ADI_V(10, 2, 8, 4, 1),
+    ADI_V(20, 8, 16, 1, 1), ADI_V(10, 8, 8, 2, 1), ADI_V(5, 4, 16, 2, 1),
+    // small lines (tests, single layout, batch sizes)
+    ADI_V(3, 1, 1, 1, 4), ADI_V(6, 2, 1, 1, 4), ADI_V(3, 2, 1, 2, 4), ADI_V(4, 4, 1, 2, 4),
+    ADI_V(8, 4, 1, 1, 4), ADI_V(12, 4, 1, 1, 4), ADI_V(6, 4, 2, 1, 2), ADI_V(4, 16, 1, 1, 4),
+    ADI_V(8, 16, 1, 2, 4), ADI_V(10, 8, 2, 1, 2), ADI_V(5, 8, 4, 2, 1), ADI_V(10, 16, 4, 1, 1),
+    ADI_V(15, 16, 8, 1, 1), ADI_V(8, 16, 4, 2, 1), ADI_V(12, 16, 2, 1, 2),
+    // long lines (up to 8192 cells)
+    ADI_V(8, 1, 4, 2, 1), ADI_V(16, 1, 4, 1, 1), ADI_V(12, 4, 16, 1, 1), ADI_V(6, 2, 16, 2, 1),
+    ADI_V(32, 4, 16, 1, 1),
 };
 #undef ADI_V
 static const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-static int find_variant(int M, int LPW, int WPL) {
-  int best = -1;
+static int find_variant(int M, int LPW, int WPL, int R, int NGW) {
   for (int v = 0; v < kNumVariants; ++v) {
     const Variant& V = kVariants[v];
-    if (V.LPW == LPW && V.WPL == WPL && V.MM >= M && (best < 0 || V.MM < kVariants[best].MM)) best = v;
+    if (V.M == M && V.LPW == LPW && V.WPL == WPL && V.R == R && V.NGW == NGW) return v;
   }
-  return best;
+  return -1;
 }
 
 }  // namespace adi
@@ -291,8 +314,8 @@ using namespace adi;
 namespace {
 
 struct Launch {
-  int M = 0, LPW = 0, WPL = 0, NGW = 1;  // shape
-  int G = 0, CPW = 0, variant = -1;
+  int M = 0, LPW = 0, WPL = 0, R = 1, NGW = 1;  // shape
+  int G = 0, variant = -1;
 };
 
 struct DirState {
@@ -303,27 +326,21 @@ struct DirState {
   DirTabs view() const {
     DirTabs d;
     d.tabs = tabs; d.pos = pos; d.chk = chk; d.eng = eng; d.xc = xc; d.work = work;
-    d.ncls = ncls; d.n = n; d.G = L.G; d.M = L.M; d.CPW = L.CPW;
+    d.ncls = ncls; d.n = n; d.G = L.G; d.M = L.M;
     return d;
   }
 };
 
-adi_status validate_launch(int n, int chunk, int lpw, int wpl, int ngw, Launch* out) {
-  if (lpw != 1 && lpw != 2 && lpw != 4 && lpw != 8 && lpw != 16)
-    return fail(ADI_EINVAL, "lines_per_wave must be 1, 2, 4, 8 or 16 (got %d)", lpw);
-  if (wpl != 1 && wpl != 2 && wpl != 4 && wpl != 8 && wpl != 16)
-    return fail(ADI_EINVAL, "waves_per_line must be 1, 2, 4, 8 or 16 (got %d)", wpl);
-  if (ngw < 1 || 64 * wpl * ngw > 1024)
-    return fail(ADI_EINVAL, "groups_per_block %d gives more than 1024 threads", ngw);
-  if (chunk < 3) return fail(ADI_EINVAL, "chunk must be >= 3 (got %d)", chunk);
-  const int cpw = 64 / lpw, G = cpw * wpl;
+adi_status validate_launch(int n, int chunk, int lpw, int wpl, int r, int ngw, Launch* out) {
+  const int v = find_variant(chunk, lpw, wpl, r, ngw);
+  if (v < 0)
+    return fail(ADI_EUNSUPPORTED, "no kernel for chunk %d, %d lines/wave, %d waves/line, %d lines/lane, "
+                "%d groups/block", chunk, lpw, wpl, r, ngw);
+  const int G = (64 / lpw) * wpl;
   if ((long)G * chunk < n)
     return fail(ADI_EINVAL, "%d chunks of %d cells do not cover a line of %d", G, chunk, n);
-  const int v = find_variant(chunk, lpw, wpl);
-  if (v < 0)
-    return fail(ADI_EUNSUPPORTED, "no kernel for chunk %d, %d lines/wave, %d waves/line", chunk, lpw, wpl);
-  out->M = chunk; out->LPW = lpw; out->WPL = wpl; out->NGW = ngw;
-  out->G = G; out->CPW = cpw; out->variant = v;
+  out->M = chunk; out->LPW = lpw; out->WPL = wpl; out->R = r; out->NGW = ngw;
+  out->G = G; out->variant = v;
   return ADI_OK;
 }
 
@@ -335,21 +352,18 @@ Launch default_launch(int dir, int n, int nlines) {
   double best_score = -1e300;
   for (int v = 0; v < kNumVariants; ++v) {
     const Variant& V = kVariants[v];
-    const int cpw = 64 / V.LPW, G = cpw * V.WPL;
-    const int M = std::max(3, (n + G - 1) / G);
-    if (M > V.MM) continue;
-    if (V.LPW > nlines && V.LPW > 1) continue;
-    double score = 0.0;
-    score -= 2.0 * (V.MM - M);                    // wasted unrolled slots
-    score -= 4.0 * std::fabs(std::log2((double)M / 16.0));  // ~16 cells per lane
-    if (dir == 1) score += 3.0 * std::log2((double)V.LPW);
-    else score -= 1.0 * std::log2((double)V.LPW);
-    score -= 0.5 * std::log2((double)V.WPL);
+    const int G = (64 / V.LPW) * V.WPL;
+    if ((long)G * V.M < n) continue;
+    const double pad = (double)G * V.M / n;                     // >= 1
+    const double lines = (double)V.LPW * V.R * V.NGW;            // lines per workgroup pass
+    double score = -8.0 * std::log2(pad);                       // wasted padded cells
+    score -= 1.0 * std::fabs(std::log2((double)V.M * V.R / 16.0));  // ~16 cells per lane
+    score -= 2.0 * std::max(0.0, std::log2(lines / std::max(1, nlines / 64)));  // keep >= 64 groups
+    if (dir == 1) score += 1.0 * std::log2((double)V.LPW * V.R);   // adjacent columns per row
     if (score > best_score) {
       best_score = score;
       Launch L;
-      L.M = M; L.LPW = V.LPW; L.WPL = V.WPL; L.G = G; L.CPW = cpw; L.variant = v;
-      L.NGW = std::max(1, 256 / (64 * V.WPL));
+      L.M = V.M; L.LPW = V.LPW; L.WPL = V.WPL; L.R = V.R; L.NGW = V.NGW; L.G = G; L.variant = v;
       best = L;
     }
   }
@@ -378,6 +392,8 @@ struct adi_problem_s {
   double *T = nullptr, *dA = nullptr, *dB = nullptr, *mid = nullptr;
   double *part = nullptr, *eout = nullptr, *state = nullptr, *prof = nullptr;
   uint8_t* dmap = nullptr;
+  int* dranges = nullptr;
+  int ranges[17] = {0};
   int check_every = 0;
   double check_tol = 1e-9;
   int64_t steps = 0;
@@ -410,8 +426,12 @@ void drop_graphs(adi_problem p) {
 
 adi_status build_geometry_once(adi_problem p) {
   if (p->geom_built) return ADI_OK;
-  hipLaunchKernelGGL(k_geometry, dim3(1), dim3(256), 0, p->stream, p->P, p->d_rfi, p->d_zfi, p->g);
+  hipLaunchKernelGGL(k_geometry, dim3(1), dim3(256), 0, p->stream, p->P, p->d_rfi, p->d_zfi, p->g,
+                     p->dranges);
   ADI_CHECK_LAUNCH();
+  ADI_HIP(hipMemcpyAsync(p->ranges, p->dranges, sizeof p->ranges, hipMemcpyDeviceToHost, p->stream));
+  ADI_HIP(hipStreamSynchronize(p->stream));
+  if (p->ranges[16]) return fail(ADI_EINVAL, "a line class is not one contiguous range of lines");
   p->geom_built = true;
   return ADI_OK;
 }
@@ -482,18 +502,29 @@ adi_status launch_sweep(adi_problem p, int dir, const double* din, double* dout,
   a.dout = dout;
   a.xout = xout;
   a.tabs = D.tabs;
-  a.line_class = dir == 0 ? p->g.bet : p->g.kap;
   a.pos_xclass = dir == 0 ? p->g.kap : p->g.bet;
   a.xc = dir == 0 ? p->z.xc : p->r.xc;  // r sweep adds b_z, z sweep adds b_r
   a.line_stride = dir == 0 ? p->P.nr : 1;
   a.pos_stride = dir == 0 ? 1 : p->P.nr;
   a.nlines = D.nlines;
-  a.ngroups = (D.nlines + D.L.LPW - 1) / D.L.LPW;
+  a.ncls = D.ncls;
+  const int per_group = D.L.LPW * D.L.R;
+  int g0 = 0;
+  for (int c = 0; c < D.ncls; ++c) {
+    const int* rg = p->ranges + (dir * MAX_CLS + c) * 2;
+    a.cls_l0[c] = rg[0];
+    a.cls_l1[c] = rg[1];
+    a.cls_g0[c] = g0;
+    g0 += (rg[1] - rg[0] + per_group - 1) / per_group;
+  }
+  for (int c = D.ncls; c < MAX_CLS; ++c) a.cls_l0[c] = a.cls_l1[c] = 0, a.cls_g0[c] = g0;
+  a.cls_g0[MAX_CLS] = g0;
+  a.cls_g0[D.ncls] = g0;
+  a.ngroups = g0;
   const Variant& V = kVariants[D.L.variant];
   const int threads = 64 * D.L.WPL * D.L.NGW;
-  const int blocks = std::max(1, std::min((a.ngroups + D.L.NGW - 1) / D.L.NGW, 1 << 20));
-  const size_t shm = sizeof(double) * D.L.NGW * D.L.LPW * D.L.WPL;
-  hipLaunchKernelGGL(V.fn, dim3(blocks), dim3(threads), shm, p->stream, a, D.L.NGW);
+  const int blocks = std::max(1, (a.ngroups + D.L.NGW - 1) / D.L.NGW);
+  hipLaunchKernelGGL(V.fn, dim3(blocks), dim3(threads), 0, p->stream, a);
   ADI_CHECK_LAUNCH();
   return ADI_OK;
 }
@@ -707,6 +738,7 @@ adi_status adi_create_problem(const adi_geometry* g, const adi_bc* bc, adi_schem
   if ((st = dev_alloc((void**)&p->state, sizeof(double) * 8, p->stream)) != ADI_OK) return cleanup(st);
   if ((st = dev_alloc((void**)&p->prof, sizeof(double) * 4096, p->stream)) != ADI_OK) return cleanup(st);
   if ((st = dev_alloc((void**)&p->dmap, n, p->stream)) != ADI_OK) return cleanup(st);
+  if ((st = dev_alloc((void**)&p->dranges, sizeof p->ranges, p->stream)) != ADI_OK) return cleanup(st);
   // line classes: r lines by row band (3), z lines by column class (4)
   p->r.n = nr; p->r.nlines = nz; p->r.ncls = 3;
   p->z.n = nz; p->z.nlines = nr; p->z.ncls = 4;
@@ -940,16 +972,16 @@ adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_
 }
 
 adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lines_per_wave,
-                          int32_t waves_per_line, int32_t groups_per_block) {
+                          int32_t waves_per_line, int32_t lines_per_lane, int32_t groups_per_block) {
   ADI_TRY(check_handle(p));
   if (dir != 0 && dir != 1) return fail(ADI_EINVAL, "dir must be 0 (r) or 1 (z)");
   DirState& D = dir == 0 ? p->r : p->z;
   Launch L;
-  ADI_TRY(validate_launch(D.n, chunk, lines_per_wave, waves_per_line, groups_per_block, &L));
-  const bool shape_change = L.G != D.L.G || L.M != D.L.M || L.CPW != D.L.CPW;
+  ADI_TRY(validate_launch(D.n, chunk, lines_per_wave, waves_per_line, lines_per_lane, groups_per_block, &L));
+  const bool shape_change = L.G != D.L.G || L.M != D.L.M;
   D.L = L;
   if (shape_change) {
-    // tables depend on the chunking: rebuild (and re-derive the carried
+    // tables depend on the chunking: rebuild them (and re-derive the carried
     // right-hand side from T) before the next step
     ADI_HIP(hipStreamSynchronize(p->stream));
     dev_free(p->tab_mem);
@@ -961,14 +993,27 @@ adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lin
 }
 
 adi_status adi_get_launch(adi_problem p, int32_t dir, int32_t* chunk, int32_t* lines_per_wave,
-                          int32_t* waves_per_line, int32_t* groups_per_block) {
+                          int32_t* waves_per_line, int32_t* lines_per_lane, int32_t* groups_per_block) {
   ADI_TRY(check_handle(p));
   if (dir != 0 && dir != 1) return fail(ADI_EINVAL, "dir must be 0 (r) or 1 (z)");
   const Launch& L = (dir == 0 ? p->r : p->z).L;
   if (chunk) *chunk = L.M;
   if (lines_per_wave) *lines_per_wave = L.LPW;
   if (waves_per_line) *waves_per_line = L.WPL;
+  if (lines_per_lane) *lines_per_lane = L.R;
   if (groups_per_block) *groups_per_block = L.NGW;
+  return ADI_OK;
+}
+
+adi_status adi_launch_shapes(int32_t* out, int32_t max_shapes, int32_t* count) {
+  if (!count) return fail(ADI_EINVAL, "null count");
+  if (max_shapes > 0 && !out) return fail(ADI_EINVAL, "null output array");
+  for (int v = 0; v < kNumVariants && v < max_shapes; ++v) {
+    const Variant& V = kVariants[v];
+    const int32_t f[5] = {V.M, V.LPW, V.WPL, V.R, V.NGW};
+    for (int q = 0; q < 5; ++q) out[5 * v + q] = f[q];
+  }
+  *count = kNumVariants;
   return ADI_OK;
 }
 
@@ -979,7 +1024,7 @@ void adi_destroy(adi_problem p) {
   else (void)hipDeviceSynchronize();
   drop_graphs(p);
   void* bufs[] = {p->d_rfi, p->d_zfi, p->geom_mem, p->tab_mem, p->T, p->dA, p->dB, p->mid,
-                  p->part, p->eout, p->state, p->prof, p->dmap};
+                  p->part, p->eout, p->state, p->prof, p->dmap, p->dranges};
   for (void* b : bufs) dev_free(b);
   if (p->own_stream) (void)hipStreamDestroy(p->stream);
   delete p;

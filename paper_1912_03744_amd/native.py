@@ -76,9 +76,10 @@ _SIGS = {
     "adi_energy": [_vp, ctypes.POINTER(EnergyReport)],
     "adi_time_sweeps": [_vp, ctypes.c_double, ctypes.c_int32, _fp, _fp],
     "adi_set_launch": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                       ctypes.c_int32],
-    "adi_get_launch": [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p],
+                       ctypes.c_int32, ctypes.c_int32],
+    "adi_get_launch": [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p],
     "adi_set_graph_steps": [_vp, ctypes.c_int32],
+    "adi_launch_shapes": [_i32p, ctypes.c_int32, _i32p],
     "adi_destroy": [_vp],
     "adi_status_string": [ctypes.c_int],
     "adi_last_error": [],
@@ -222,14 +223,25 @@ class Problem:
         check(lib().adi_time_sweeps(self._h, float(dt), int(nlaunch), ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
-    def set_launch(self, direction, chunk, lines_per_wave, waves_per_line, groups_per_block=1):
+    def set_launch(self, direction, chunk, lines_per_wave, waves_per_line, lines_per_lane=1,
+                   groups_per_block=1):
         check(lib().adi_set_launch(self._h, int(direction), int(chunk), int(lines_per_wave),
-                                   int(waves_per_line), int(groups_per_block)))
+                                   int(waves_per_line), int(lines_per_lane), int(groups_per_block)))
 
     def get_launch(self, direction):
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32() for _ in range(5)]
         check(lib().adi_get_launch(self._h, int(direction), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
+
+
+def launch_shapes():
+    """Compiled (chunk, lines_per_wave, waves_per_line, lines_per_lane,
+    groups_per_block) shapes."""
+    n = ctypes.c_int32()
+    check(lib().adi_launch_shapes(None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_int32 * (5 * n.value))()
+    check(lib().adi_launch_shapes(buf, n.value, ctypes.byref(n)))
+    return [tuple(buf[5 * i:5 * i + 5]) for i in range(n.value)]
 
 
 def version():

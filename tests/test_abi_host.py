@@ -32,6 +32,14 @@ def test_library_exports_every_declared_function(native):
     assert set(native.exported_symbols()) <= set(names)
 
 
+def test_launch_shapes_listed(native):
+    shapes = native.launch_shapes()
+    assert len(shapes) >= 10
+    for m, lpw, wpl, r, ngw in shapes:
+        assert m >= 3 and lpw in (1, 2, 4, 8, 16) and wpl in (1, 2, 4, 8, 16)
+        assert r >= 1 and 64 * wpl * ngw <= 1024
+
+
 def test_status_strings(native):
     lib = native.lib()
     for code in range(0, -8, -1):
