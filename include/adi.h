@@ -174,6 +174,56 @@ adi_status adi_set_graph_steps(adi_problem p, int32_t steps);
 
 void adi_destroy(adi_problem p);
 
+/* ------------------------------------------------------- ragged batch -- */
+
+/* A batch of n independent instances (the design sweep): instance i has its
+ * own geometry geoms[i] (uniform grid, 3 <= nr <= 192, 3 <= nz <= 480;
+ * face arrays are not supported here) and films bcs[i].  All instances are
+ * advanced together by one persistent kernel launch: each workgroup takes
+ * the next instance from an atomic queue (largest grids first), builds its
+ * geometry and factor tables, runs the whole time loop and takes the next.
+ * Errors: ADI_EINVAL, ADI_EUNSUPPORTED (grid or face arrays), ADI_ENOMEM. */
+adi_status adi_create_batch(int32_t n, const adi_geometry* geoms, const adi_bc* bcs, adi_scheme scheme,
+                            void* hip_stream, adi_batch* out);
+
+/* Per-instance materials and sources, n*5 values each (instance-major):
+ * k > 0, rho_c > 0, finite q (eq. 1-2 with constant coefficients). */
+adi_status adi_batch_set_materials(adi_batch b, const double* k, const double* rho_c, const double* q);
+
+/* Uniform initial temperature per instance (n values; NULL = all 0). */
+adi_status adi_batch_set_initial(adi_batch b, const double* T0);
+
+/* Launch shape of the batch kernel (the autotuner uses it): lines per lane
+ * (1 or 2), waves per workgroup (4 or 8), resident workgroups per compute
+ * unit (1..8).  ADI_EUNSUPPORTED for shapes not compiled. */
+adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t waves_per_block,
+                                int32_t blocks_per_cu);
+
+/* Advance every instance nsteps steps of size dt from its initial field
+ * (each call starts again from the initial fields), recording the outer
+ * terminal-face profile (top row resampled at r_k = (k+0.5)*rmax/npts, as in
+ * adi_read_profile) after every snapshot_every-th step (0 = none).  Enqueued
+ * on the batch's stream as one captured HIP graph (queue reset + persistent
+ * kernel); returns without waiting. */
+adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapshot_every, int32_t npts);
+
+/* Wait for the batch's stream. */
+adi_status adi_batch_sync(adi_batch b);
+
+/* Profiles of the last adi_batch_step: count = n * (nsteps/snapshot_every) *
+ * npts doubles, instance-major, then snapshot, then point.  Synchronises. */
+adi_status adi_batch_read_profiles(adi_batch b, double* host_out, size_t count);
+
+/* Final field of instance i (nz*nr doubles, r fastest; cells outside the
+ * domain hold 0).  Synchronises. */
+adi_status adi_batch_read_field(adi_batch b, int32_t i, double* host_out, size_t count);
+
+/* Total cells over all instances, snapshots per instance of the last step,
+ * persistent workgroups launched. */
+adi_status adi_batch_info(adi_batch b, int64_t* total_cells, int32_t* nsnap, int32_t* workgroups);
+
+void adi_batch_destroy(adi_batch b);
+
 /* ---------------------------------------------------------- utilities -- */
 
 const char* adi_status_string(adi_status s);

@@ -158,11 +158,13 @@ __device__ __forceinline__ void axis_point(int i, int n, double length, const do
 }
 
 // Fill the geometry arrays; called by one workgroup (any size).  ranges
-// receives, per direction (0: rows by band, 1: columns by class) and class,
-// the index range [first, last+1) of its lines; ranges[16] is set to 1 if a
-// class is not one contiguous range (centres are monotone, so never).
+// (17 ints, any memory) receives, per direction (0: rows by band, 1: columns
+// by class) and class, the index range [first, last+1) of its lines; a class
+// with no lines gets [0, 0).  ranges[16] is set non-zero if a class is not
+// one contiguous run (centres are monotone, so it never is).
 __device__ void build_geometry(const Params& P, const double* rfaces_in, const double* zfaces_in,
                                const Geom& g, int* ranges) {
+  for (int q = threadIdx.x; q < 17; q += blockDim.x) ranges[q] = 0;
   for (int i = threadIdx.x; i < P.nr; i += blockDim.x) {
     axis_point(i, P.nr, P.rmax, rfaces_in, g.rf, g.rc, g.dr);
     g.kap[i] = (uint8_t)column_class(P, g.rc[i]);
@@ -171,28 +173,26 @@ __device__ void build_geometry(const Params& P, const double* rfaces_in, const d
     axis_point(j, P.nz, P.ztop, zfaces_in, g.zf, g.zc, g.dz);
     g.bet[j] = (uint8_t)row_band(P, g.zc[j]);
   }
+  __shared__ int cnt[2 * MAX_CLS];
+  for (int q = threadIdx.x; q < 2 * MAX_CLS; q += blockDim.x) cnt[q] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int bad = 0;
-    for (int dir = 0; dir < 2; ++dir) {
-      const uint8_t* cl = dir == 0 ? g.bet : g.kap;
-      const int n = dir == 0 ? P.nz : P.nr;
-      for (int c = 0; c < MAX_CLS; ++c) {
-        int lo = -1, hi = -1, cnt = 0;
-        for (int q = 0; q < n; ++q)
-          if (cl[q] == c) {
-            if (lo < 0) lo = q;
-            hi = q + 1;
-            ++cnt;
-          }
-        if (cnt == 0) lo = hi = 0;
-        if (cnt != hi - lo) bad = 1;
-        ranges[(dir * MAX_CLS + c) * 2] = lo;
-        ranges[(dir * MAX_CLS + c) * 2 + 1] = hi;
-      }
+  // run boundaries: where the class changes along each axis
+  for (int dir = 0; dir < 2; ++dir) {
+    const uint8_t* cl = dir == 0 ? g.bet : g.kap;
+    const int n = dir == 0 ? P.nz : P.nr;
+    int* rg = ranges + dir * MAX_CLS * 2;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+      const int c = cl[q];
+      atomicAdd(&cnt[dir * MAX_CLS + c], 1);
+      if (q == 0 || cl[q - 1] != c) rg[2 * c] = q;
+      if (q == n - 1 || cl[q + 1] != c) rg[2 * c + 1] = q + 1;
     }
-    ranges[16] = bad;
   }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 2 * MAX_CLS; ++q)
+      if (cnt[q] != ranges[2 * q + 1] - ranges[2 * q]) ranges[16] = 1;
+  __syncthreads();
 }
 
 // ------------------------------------------------------------- assembly --

@@ -81,11 +81,22 @@ _SIGS = {
     "adi_set_graph_steps": [_vp, ctypes.c_int32],
     "adi_launch_shapes": [_i32p, ctypes.c_int32, _i32p],
     "adi_destroy": [_vp],
+    "adi_create_batch": [ctypes.c_int32, ctypes.POINTER(Geometry), ctypes.POINTER(BC), ctypes.c_int,
+                         _vp, ctypes.POINTER(_vp)],
+    "adi_batch_set_materials": [_vp, _dp, _dp, _dp],
+    "adi_batch_set_initial": [_vp, _dp],
+    "adi_batch_set_launch": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "adi_batch_step": [_vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32],
+    "adi_batch_sync": [_vp],
+    "adi_batch_read_profiles": [_vp, _dp, ctypes.c_size_t],
+    "adi_batch_read_field": [_vp, ctypes.c_int32, _dp, ctypes.c_size_t],
+    "adi_batch_info": [_vp, ctypes.POINTER(ctypes.c_int64), _i32p, _i32p],
+    "adi_batch_destroy": [_vp],
     "adi_status_string": [ctypes.c_int],
     "adi_last_error": [],
     "adi_version": [],
 }
-_RESTYPE = {"adi_destroy": None, "adi_status_string": ctypes.c_char_p,
+_RESTYPE = {"adi_destroy": None, "adi_batch_destroy": None, "adi_status_string": ctypes.c_char_p,
             "adi_last_error": ctypes.c_char_p, "adi_version": ctypes.c_char_p}
 
 _LIB = None
@@ -232,6 +243,69 @@ class Problem:
         v = [ctypes.c_int32() for _ in range(5)]
         check(lib().adi_get_launch(self._h, int(direction), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
+
+
+class Batch:
+    """A ragged batch of independent instances (adi_create_batch ...)."""
+
+    def __init__(self, specs, scheme="pr", stream=None):
+        n = len(specs)
+        geoms = (Geometry * n)()
+        bcs = (BC * n)()
+        for i, s in enumerate(specs):
+            if s.r_faces is not None or s.z_faces is not None:
+                raise ValueError("batches use uniform grids")
+            geoms[i] = Geometry(*[float(x) for x in s.geom], int(s.nr), int(s.nz), None, None)
+            bcs[i] = BC((ctypes.c_double * 4)(*[float(x) for x in s.h]),
+                        (ctypes.c_double * 4)(*[float(x) for x in s.t_inf]))
+        h = _vp()
+        st = stream if stream is not None else current_stream()
+        check(lib().adi_create_batch(n, geoms, bcs, SCHEMES[scheme], st, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.shapes = [(int(s.nr), int(s.nz)) for s in specs]
+        k = _f64([s.k for s in specs], 5 * n)
+        rc = _f64([s.rhoc for s in specs], 5 * n)
+        q = _f64([s.q for s in specs], 5 * n)
+        check(lib().adi_batch_set_materials(self._h, _ptr(k), _ptr(rc), _ptr(q)))
+        t0 = _f64([s.T0 for s in specs], n)
+        check(lib().adi_batch_set_initial(self._h, _ptr(t0)))
+        self._nsnap, self._npts = 0, 64
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().adi_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_launch(self, lines_per_lane, waves_per_block, blocks_per_cu):
+        check(lib().adi_batch_set_launch(self._h, int(lines_per_lane), int(waves_per_block),
+                                         int(blocks_per_cu)))
+
+    def step(self, dt, nsteps, snapshot_every=0, npts=64):
+        check(lib().adi_batch_step(self._h, float(dt), int(nsteps), int(snapshot_every), int(npts)))
+        self._nsnap = int(nsteps) // int(snapshot_every) if snapshot_every else 0
+        self._npts = int(npts)
+
+    def sync(self):
+        check(lib().adi_batch_sync(self._h))
+
+    def profiles(self):
+        out = np.empty((self.n, self._nsnap, self._npts))
+        check(lib().adi_batch_read_profiles(self._h, _ptr(out), out.size))
+        return out
+
+    def field(self, i):
+        nr, nz = self.shapes[i]
+        out = np.empty((nz, nr))
+        check(lib().adi_batch_read_field(self._h, int(i), _ptr(out), out.size))
+        return out
+
+    def info(self):
+        tc, ns, wg = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().adi_batch_info(self._h, ctypes.byref(tc), ctypes.byref(ns), ctypes.byref(wg)))
+        return {"total_cells": tc.value, "nsnap": ns.value, "workgroups": wg.value}
 
 
 def launch_shapes():

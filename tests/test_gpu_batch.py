@@ -1,0 +1,89 @@
+"""GPU parity of the ragged-batch path: every instance of a batch (own
+geometry, materials and grid size) against the CPU oracle run alone, plus
+batch-vs-single consistency, snapshot profiles and queue coverage."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import gpu_available, rel_inf
+from paper_1912_03744_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+TOL = 1e-12
+
+
+def _oracle_run(s, nsteps):
+    P = oracle.Problem.from_spec(s)
+    T, _ = P.step(P.initial(s.T0), s.scheme, s.dt, nsteps)
+    return P, T
+
+
+@pytest.mark.parametrize("scheme", ["pr", "lod"])
+def test_batch_instances_match_oracle(scheme):
+    """A stratified ragged batch (every size class, seeded designs) after 60
+    steps with profiles every 20 steps, each instance against the oracle."""
+    from paper_1912_03744_amd import native
+    specs = W.ragged_batch(24, master_seed=5, scheme=scheme, dt=1e-3, nsteps=60)
+    specs[3] = specs[3].replace(t_inf=(0.0, 0.3, -0.2, 0.1), T0=0.4)  # non-zero ambient and start
+    b = native.Batch(specs, scheme=scheme)
+    b.step(1e-3, 60, snapshot_every=20, npts=64)
+    prof = b.profiles()
+    assert prof.shape == (24, 3, 64)
+    print("batch %s: %s" % (scheme, b.info()), flush=True)
+    for i, s in enumerate(specs):
+        P, want = _oracle_run(s, 60)
+        got = b.field(i)
+        act = P.active()
+        assert rel_inf(got, want, act) <= TOL, (i, s.nr, s.nz)
+        assert np.all(got[~act] == 0.0)
+        wp = P.profile(want, 0, 64)
+        assert np.max(np.abs(prof[i, 2] - wp)) <= TOL * np.max(np.abs(wp))
+        if i < 6:  # intermediate snapshot
+            P2, w20 = _oracle_run(s, 20)
+            wp20 = P2.profile(w20, 0, 64)
+            assert np.max(np.abs(prof[i, 0] - wp20)) <= TOL * np.max(np.abs(wp20))
+
+
+def test_batch_odd_sizes_and_launch_shapes():
+    """Grid sizes between the compiled line shapes and tiny grids, under every
+    batch launch shape; more instances than persistent workgroups."""
+    from paper_1912_03744_amd import native
+    rng = np.random.default_rng(1)
+    base = W.ragged_batch(40, master_seed=9, nsteps=15)
+    sizes = [(3, 3), (5, 7), (64, 160), (65, 161), (97, 241), (129, 321), (191, 479), (192, 480), (33, 400)]
+    specs = [s.replace(nr=sizes[i % len(sizes)][0], nz=sizes[i % len(sizes)][1]) for i, s in enumerate(base)]
+    want = [_oracle_run(s, 15) for s in specs]
+    for shape in ((1, 4, 1), (2, 4, 2), (1, 8, 1), (2, 8, 1)):
+        b = native.Batch(specs)
+        b.set_launch(*shape)
+        b.step(1e-3, 15)
+        for i in rng.choice(len(specs), 12, replace=False):
+            P, w = want[i]
+            assert rel_inf(b.field(int(i)), w, P.active()) <= TOL, (shape, i, specs[i].nr, specs[i].nz)
+
+
+def test_batch_equals_single_instance_path():
+    """Instance k of a batch reaches the single-instance GPU result (same
+    method, different launch decomposition) to the parity tolerance."""
+    from paper_1912_03744_amd import native
+    specs = W.ragged_batch(8, master_seed=3, nsteps=40)
+    b = native.Batch(specs)
+    b.step(1e-3, 40)
+    for i in (0, 5):
+        p = native.Problem.from_spec(specs[i])
+        p.step(1e-3, 40)
+        single = p.read_field()
+        act = ~np.isnan(single)
+        assert rel_inf(b.field(i), single, act) <= TOL
+
+
+def test_batch_errors():
+    from paper_1912_03744_amd import native
+    s = W.ragged_batch(2, master_seed=0)
+    with pytest.raises(native.AdiError):
+        native.Batch([s[0].replace(nr=193)])
+    b = native.Batch(s)
+    with pytest.raises(native.AdiError):
+        b.set_launch(3, 4, 1)
+    with pytest.raises(native.AdiError):
+        b.step(-1.0, 10)
