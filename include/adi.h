@@ -224,6 +224,48 @@ adi_status adi_batch_info(adi_batch b, int64_t* total_cells, int32_t* nsnap, int
 
 void adi_batch_destroy(adi_batch b);
 
+/* ---------------------------------------------------- learned surrogate -- */
+
+/* Multilayer perceptron x -> gelu(x W_1 + b_1) -> ... -> h W_out + b_out with
+ * gelu(u) = u Phi(u) (erf form).  widths[0] inputs (1..64), then nwidths-1
+ * layer widths (multiples of 64, <= 4096); at most 8 layers.  Weights are
+ * initialised from `seed` (He-normal, zero biases).  Products run on bf16
+ * matrix cores with fp32 accumulation; hidden activations are kept in bf16,
+ * the output and pre-activations in fp32; fp32 master weights and Adam
+ * (beta 0.9/0.999, eps 1e-8).  The flat parameter vector holds, layer by
+ * layer, W_l ([n_in x n_out] row-major) then b_l. */
+adi_status adi_mlp_create(const int32_t* widths, int32_t nwidths, uint64_t seed, void* hip_stream,
+                          adi_mlp* out);
+adi_status adi_mlp_num_params(adi_mlp m, int64_t* n);
+
+/* Input encoding applied on the device: x' = (x - shift) * scale per feature
+ * (widths[0] values each). */
+adi_status adi_mlp_set_scaling(adi_mlp m, const float* shift, const float* scale);
+
+/* Parameters as fp32 host arrays (count = number of parameters).  set resets
+ * the optimiser state. */
+adi_status adi_mlp_get_params(adi_mlp m, float* host_out, int64_t count);
+adi_status adi_mlp_set_params(adi_mlp m, const float* host_in, int64_t count);
+
+/* y = network(x): dev_x [batch x widths[0]] fp32 and dev_y [batch x
+ * widths[last]] fp32 are device pointers; batch is a multiple of 64.
+ * Asynchronous on the network's stream. */
+adi_status adi_mlp_forward(adi_mlp m, const float* dev_x, int64_t batch, float* dev_y);
+
+/* Mean-squared-error loss against dev_t and its gradient w.r.t. every
+ * parameter (copied to host_grads, nullable); loss_out (host, nullable).
+ * Synchronises. */
+adi_status adi_mlp_gradients(adi_mlp m, const float* dev_x, const float* dev_t, int64_t batch,
+                             float* host_grads, float* loss_out);
+
+/* One training step: forward, backward, Adam with learning rate lr.  If
+ * loss_out is not NULL the loss before the update is written there (and the
+ * call synchronises). */
+adi_status adi_mlp_train_step(adi_mlp m, const float* dev_x, const float* dev_t, int64_t batch, float lr,
+                              float* loss_out);
+
+void adi_mlp_destroy(adi_mlp m);
+
 /* ---------------------------------------------------------- utilities -- */
 
 const char* adi_status_string(adi_status s);

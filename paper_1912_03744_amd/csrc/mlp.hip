@@ -1,0 +1,590 @@
+// mlp.hip -- the learned surrogate: a GELU multilayer perceptron trained and
+// evaluated with bf16 matrix cores (v_mfma_f32_32x32x16_bf16) and fp32
+// accumulation, fp32 master weights and Adam.
+//
+// Network: x (n0 features) -> h_l = gelu(h_{l-1} W_l + b_l) for the hidden
+// layers -> y = h_L W_out + b_out.  gelu(u) = u Phi(u) (erf form).  Hidden
+// activations are stored in bf16 (the next product's operand), the output
+// and all pre-activations in fp32.  Loss: mean squared error over batch and
+// outputs.  Weights W_l are [n_in x n_out] row-major; the flat parameter
+// vector holds, layer by layer, W_l then b_l.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "common.hpp"
+
+namespace adi {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 64, BN = 64, KT = 32, LDP = KT + 8;  // tile sizes; padded LDS rows (bf16)
+constexpr int MAX_LAYERS = 8;
+constexpr int KPAD = 64;                                 // input features padded to a whole tile
+
+enum Epi { EPI_HIDDEN = 0, EPI_OUTPUT = 1, EPI_DGELU = 2, EPI_PARTIAL = 3 };
+
+struct GemmArgs {
+  const __bf16* A;  // [M][K] (a_kmajor) or [K][M]
+  long lda;
+  const __bf16* B;  // [N][K] (b_kmajor) or [K][N]
+  long ldb;
+  int M, N, K, Ks;  // K per split (grid.z splits)
+  const float* bias;
+  const float* U;   // pre-activations for EPI_DGELU
+  float* out_f32;
+  __bf16* out_bf16;
+  long ldo;
+  long split_stride;
+};
+
+__device__ __forceinline__ float gelu_f(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float u) {
+  return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * 0.39894228040143268f * expf(-0.5f * u * u);
+}
+
+// C[m][n] = sum_k A[m][k] B[k][n] over this block's K range, 64 x 64 tile per
+// workgroup, one 32 x 32 bf16 MFMA accumulator per wave.
+template <bool AK, bool BK, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[BM][LDP];  // [m][k]
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][LDP];  // [n][k]
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int kbeg = blockIdx.z * g.Ks;
+  const int kend = min(g.K, kbeg + g.Ks);
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  floatx16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    // stage A (64 x 32) and B (32 x 64) tiles: 256 threads x 8 bf16 each
+    if (AK) {
+      const int row = t >> 2, kq = (t & 3) * 8;
+      *(bf16x8*)&As[row][kq] = *(const bf16x8*)(g.A + (long)(m0 + row) * g.lda + k0 + kq);
+    } else {
+      const int kr = t >> 3, mq = (t & 7) * 8;
+      const bf16x8 v = *(const bf16x8*)(g.A + (long)(k0 + kr) * g.lda + m0 + mq);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[mq + j][kr] = v[j];
+    }
+    if (BK) {
+      const int row = t >> 2, kq = (t & 3) * 8;
+      *(bf16x8*)&Bs[row][kq] = *(const bf16x8*)(g.B + (long)(n0 + row) * g.ldb + k0 + kq);
+    } else {
+      const int kr = t >> 3, nq = (t & 7) * 8;
+      const bf16x8 v = *(const bf16x8*)(g.B + (long)(k0 + kr) * g.ldb + n0 + nq);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bs[nq + j][kr] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 16) {
+      const bf16x8 a = *(const bf16x8*)&As[wm + (lane & 31)][kk + 8 * (lane >> 5)];
+      const bf16x8 b = *(const bf16x8*)&Bs[wn + (lane & 31)][kk + 8 * (lane >> 5)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // accumulator i of lane l: row 8*(i/4) + 4*(l/32) + i%4, column l%32
+  const int n = n0 + wn + (lane & 31);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int m = m0 + wm + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    const long o = (long)m * g.ldo + n;
+    const float v = acc[i];
+    if constexpr (EPI == EPI_HIDDEN) {
+      const float u = v + g.bias[n];
+      g.out_f32[o] = u;
+      g.out_bf16[o] = (__bf16)gelu_f(u);
+    } else if constexpr (EPI == EPI_OUTPUT) {
+      g.out_f32[o] = v + g.bias[n];
+    } else if constexpr (EPI == EPI_DGELU) {
+      const float d = v * gelu_grad_f(g.U[o]);
+      g.out_f32[o] = d;
+      g.out_bf16[o] = (__bf16)d;
+    } else {
+      g.out_f32[(long)blockIdx.z * g.split_stride + o] = v;
+    }
+  }
+}
+
+// x (B x nin fp32) -> (x - shift) * scale as bf16, zero-padded to KPAD columns.
+__global__ void k_encode(const float* __restrict__ x, int nin, long B, const float* shift, const float* scale,
+                         __bf16* __restrict__ out) {
+  const long n = B * KPAD;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const long r = e / KPAD;
+    const int c = (int)(e % KPAD);
+    out[e] = (__bf16)(c < nin ? (x[r * nin + c] - shift[c]) * scale[c] : 0.0f);
+  }
+}
+
+// Mean squared error: dY = 2 (Y - T) / (B * nout), per-row partial sums of
+// squares (reduced in a fixed order by k_sum_rows).
+__global__ void k_loss(const float* __restrict__ Y, const float* __restrict__ T, long B, int nout, float* dY,
+                       __bf16* dYb, float* rowsq) {
+  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < B; r += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    const float c = 2.0f / (float)((double)B * nout);
+    for (int j = 0; j < nout; ++j) {
+      const float d = Y[r * nout + j] - T[r * nout + j];
+      s += (double)d * d;
+      dY[r * nout + j] = c * d;
+      dYb[r * nout + j] = (__bf16)(c * d);
+    }
+    rowsq[r] = (float)s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sum_rows(const float* v, long n, double denom, float* out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) a += v[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)(s[0] / denom);
+}
+
+// Column sums of D (B x N fp32) into out[N]: one block per 64 columns, four
+// row phases combined in a fixed order.
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ D, long B, int N, float* out) {
+  __shared__ float s[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+  float a = 0.0f;
+  if (c < N)
+    for (long r = ph; r < B; r += 4) a += D[r * N + c];
+  s[ph][threadIdx.x & 63] = a;
+  __syncthreads();
+  if (ph == 0 && c < N) out[c] = ((s[0][threadIdx.x] + s[1][threadIdx.x]) + s[2][threadIdx.x]) + s[3][threadIdx.x];
+}
+
+// Sum the split-K partial products (fixed order) into the gradient of W,
+// keeping the first `rows` rows (the real input features of layer 1).
+__global__ void k_reduce_splits(const float* __restrict__ part, int splits, long stride, int rows, int N,
+                                float* out) {
+  const long n = (long)rows * N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    float a = 0.0f;
+    for (int s = 0; s < splits; ++s) a += part[s * stride + e];
+    out[e] = a;
+  }
+}
+
+// Adam with bias correction on fp32 master parameters.
+__global__ void k_adam(float* p, const float* g, float* m, float* v, long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// bf16 operand copies of one layer's weights: W as [kin_pad][nout] and its
+// transpose [nout][kin_pad]; rows past kin are zero.
+__global__ void k_refresh(const float* __restrict__ W, int kin, int kin_pad, int nout, __bf16* Wb, __bf16* Wtb) {
+  const long n = (long)kin_pad * nout;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / nout), j = (int)(e % nout);
+    const __bf16 v = (__bf16)(i < kin ? W[(long)i * nout + j] : 0.0f);
+    Wb[e] = v;
+    Wtb[(long)j * kin_pad + i] = v;
+  }
+}
+
+}  // namespace adi
+
+using namespace adi;
+
+struct adi_mlp_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int nl = 0;                 // number of weight layers
+  int width[MAX_LAYERS + 1];  // width[0] = inputs, width[nl] = outputs
+  int kin_pad[MAX_LAYERS];    // padded input width of each layer
+  long woff[MAX_LAYERS], boff[MAX_LAYERS], nparams = 0;
+  float *P = nullptr, *Gr = nullptr, *Mm = nullptr, *Vv = nullptr;
+  __bf16 *Wb[MAX_LAYERS] = {}, *Wtb[MAX_LAYERS] = {};
+  float *shift = nullptr, *scale = nullptr;
+  // activations for `cap` rows
+  long cap = 0;
+  __bf16* X = nullptr;
+  __bf16* H[MAX_LAYERS] = {};
+  float* U[MAX_LAYERS] = {};
+  float* Y = nullptr;
+  float* dYf = nullptr;
+  __bf16* dYb = nullptr;
+  float *dUf = nullptr, *dUf2 = nullptr;
+  __bf16 *dUb = nullptr, *dUb2 = nullptr;
+  float* rowsq = nullptr;
+  float* part = nullptr;
+  long part_cap = 0;
+  float* loss = nullptr;
+  long step = 0;
+  float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+};
+
+namespace {
+
+adi_status mlp_handle(adi_mlp m) {
+  if (!m) return fail(ADI_EINVAL, "null network handle");
+  ADI_HIP(hipSetDevice(m->device));
+  return ADI_OK;
+}
+
+template <bool AK, bool BK, int EPI>
+adi_status gemm(adi_mlp mm, const GemmArgs& g, int splits) {
+  if (g.M % BM || g.N % BN || g.K % KT || g.Ks % KT)
+    return fail(ADI_EINVAL, "internal: gemm shape %dx%dx%d not tiled", g.M, g.N, g.K);
+  hipLaunchKernelGGL((k_gemm<AK, BK, EPI>), dim3(g.M / BM, g.N / BN, splits), dim3(256), 0, mm->stream, g);
+  ADI_CHECK_LAUNCH();
+  return ADI_OK;
+}
+
+void free_acts(adi_mlp m) {
+  dev_free(m->X);
+  m->X = nullptr;
+  for (int l = 0; l < MAX_LAYERS; ++l) {
+    dev_free(m->H[l]);
+    dev_free(m->U[l]);
+    m->H[l] = nullptr;
+    m->U[l] = nullptr;
+  }
+  void* b[] = {m->Y, m->dYf, m->dYb, m->dUf, m->dUf2, m->dUb, m->dUb2, m->rowsq};
+  for (void* p : b) dev_free(p);
+  m->Y = m->dYf = m->dUf = m->dUf2 = m->rowsq = nullptr;
+  m->dYb = m->dUb = m->dUb2 = nullptr;
+  m->cap = 0;
+}
+
+adi_status ensure_acts(adi_mlp m, long B) {
+  if (B <= m->cap) return ADI_OK;
+  ADI_HIP(hipStreamSynchronize(m->stream));
+  free_acts(m);
+  long cap = ((B + 1023) / 1024) * 1024;
+  int wmax = 0;
+  for (int l = 1; l <= m->nl; ++l) wmax = std::max(wmax, m->width[l]);
+  ADI_TRY(dev_alloc((void**)&m->X, 2 * cap * KPAD, m->stream));
+  for (int l = 0; l < m->nl - 1; ++l) {
+    ADI_TRY(dev_alloc((void**)&m->H[l], 2 * cap * m->width[l + 1], m->stream));
+    ADI_TRY(dev_alloc((void**)&m->U[l], 4 * cap * m->width[l + 1], m->stream));
+  }
+  const int nout = m->width[m->nl];
+  ADI_TRY(dev_alloc((void**)&m->Y, 4 * cap * nout, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->dYf, 4 * cap * nout, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->dYb, 2 * cap * nout, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->dUf, 4 * cap * wmax, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->dUf2, 4 * cap * wmax, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->dUb, 2 * cap * wmax, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->dUb2, 2 * cap * wmax, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->rowsq, 4 * cap, m->stream));
+  m->cap = cap;
+  return ADI_OK;
+}
+
+adi_status refresh_weights(adi_mlp m) {
+  for (int l = 0; l < m->nl; ++l) {
+    const long n = (long)m->kin_pad[l] * m->width[l + 1];
+    hipLaunchKernelGGL(k_refresh, dim3((int)std::min<long>((n + 255) / 256, 1024)), dim3(256), 0, m->stream,
+                       m->P + m->woff[l], m->width[l], m->kin_pad[l], m->width[l + 1], m->Wb[l], m->Wtb[l]);
+    ADI_CHECK_LAUNCH();
+  }
+  return ADI_OK;
+}
+
+adi_status check_batch(adi_mlp m, long B) {
+  if (B < 1 || B > (1L << 26)) return fail(ADI_EINVAL, "batch must be in [1, 2^26]");
+  if (B % BM) return fail(ADI_EINVAL, "batch must be a multiple of %d", BM);
+  (void)m;
+  return ADI_OK;
+}
+
+adi_status forward(adi_mlp m, const float* x, long B) {
+  hipLaunchKernelGGL(k_encode, dim3((int)std::min<long>((B * KPAD + 255) / 256, 8192)), dim3(256), 0, m->stream,
+                     x, m->width[0], B, m->shift, m->scale, m->X);
+  ADI_CHECK_LAUNCH();
+  const __bf16* in = m->X;
+  for (int l = 0; l < m->nl; ++l) {
+    GemmArgs g{};
+    g.A = in;
+    g.lda = m->kin_pad[l];
+    g.B = m->Wtb[l];
+    g.ldb = m->kin_pad[l];
+    g.M = (int)B;
+    g.N = m->width[l + 1];
+    g.K = g.Ks = m->kin_pad[l];
+    g.bias = m->P + m->boff[l];
+    g.ldo = m->width[l + 1];
+    if (l < m->nl - 1) {
+      g.out_f32 = m->U[l];
+      g.out_bf16 = m->H[l];
+      ADI_TRY((gemm<true, true, EPI_HIDDEN>(m, g, 1)));
+      in = m->H[l];
+    } else {
+      g.out_f32 = m->Y;
+      ADI_TRY((gemm<true, true, EPI_OUTPUT>(m, g, 1)));
+    }
+  }
+  return ADI_OK;
+}
+
+// Loss, gradients of all parameters into m->Gr.
+adi_status backward(adi_mlp m, const float* target, long B) {
+  const int nout = m->width[m->nl];
+  hipLaunchKernelGGL(k_loss, dim3((int)std::min<long>((B + 255) / 256, 4096)), dim3(256), 0, m->stream, m->Y,
+                     target, B, nout, m->dYf, m->dYb, m->rowsq);
+  ADI_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, m->stream, m->rowsq, B, (double)B * nout, m->loss);
+  ADI_CHECK_LAUNCH();
+  // split-K over the batch for the weight gradients: ~256 rows per split
+  const int splits = (int)std::max<long>(1, std::min<long>(64, B / 256));
+  const long Ks = ((B / splits + KT - 1) / KT) * KT;
+  const int nsplit = (int)((B + Ks - 1) / Ks);
+  long need = 0;
+  for (int l = 0; l < m->nl; ++l) need = std::max(need, (long)nsplit * m->kin_pad[l] * m->width[l + 1]);
+  if (need > m->part_cap) {
+    ADI_HIP(hipStreamSynchronize(m->stream));
+    dev_free(m->part);
+    m->part = nullptr;
+    ADI_TRY(dev_alloc((void**)&m->part, 4 * need, m->stream));
+    m->part_cap = need;
+  }
+  const float* dF = m->dYf;     // fp32 gradient w.r.t. this layer's pre-activation
+  const __bf16* dB = m->dYb;    // same in bf16
+  for (int l = m->nl - 1; l >= 0; --l) {
+    const int kin = m->kin_pad[l], no = m->width[l + 1];
+    // dW_l = H_{l-1}^T dU_l (split over the batch), db_l = column sums
+    GemmArgs w{};
+    w.A = l > 0 ? m->H[l - 1] : m->X;
+    w.lda = kin;
+    w.B = dB;
+    w.ldb = no;
+    w.M = kin;
+    w.N = no;
+    w.K = (int)B;
+    w.Ks = (int)Ks;
+    w.out_f32 = m->part;
+    w.ldo = no;
+    w.split_stride = (long)kin * no;
+    ADI_TRY((gemm<false, false, EPI_PARTIAL>(m, w, nsplit)));
+    const long nw = (long)m->width[l] * no;
+    hipLaunchKernelGGL(k_reduce_splits, dim3((int)std::min<long>((nw + 255) / 256, 2048)), dim3(256), 0,
+                       m->stream, m->part, nsplit, (long)kin * no, m->width[l], no, m->Gr + m->woff[l]);
+    ADI_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_colsum, dim3((no + 63) / 64), dim3(256), 0, m->stream, dF, B, no, m->Gr + m->boff[l]);
+    ADI_CHECK_LAUNCH();
+    if (l == 0) break;
+    // dU_{l-1} = (dU_l W_l^T) * gelu'(U_{l-1})
+    GemmArgs d{};
+    d.A = dB;
+    d.lda = no;
+    d.B = m->Wb[l];  // [kin][no]: the transposed operand in [n][k] form
+    d.ldb = no;
+    d.M = (int)B;
+    d.N = kin;
+    d.K = d.Ks = no;
+    d.U = m->U[l - 1];
+    float* of = (dF == m->dUf) ? m->dUf2 : m->dUf;
+    __bf16* ob = (dB == m->dUb) ? m->dUb2 : m->dUb;
+    d.out_f32 = of;
+    d.out_bf16 = ob;
+    d.ldo = kin;
+    ADI_TRY((gemm<true, true, EPI_DGELU>(m, d, 1)));
+    dF = of;
+    dB = ob;
+  }
+  return ADI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adi_status adi_mlp_create(const int32_t* widths, int32_t nwidths, uint64_t seed, void* hip_stream,
+                          adi_mlp* out) {
+  if (!out) return fail(ADI_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!widths || nwidths < 2 || nwidths > MAX_LAYERS + 1) return fail(ADI_EINVAL, "need 2..%d widths", MAX_LAYERS + 1);
+  if (widths[0] < 1 || widths[0] > KPAD) return fail(ADI_EINVAL, "input width must be in [1, %d]", KPAD);
+  for (int l = 1; l < nwidths; ++l)
+    if (widths[l] < BN || widths[l] % BN || widths[l] > 4096)
+      return fail(ADI_EINVAL, "layer widths must be multiples of %d (got %d)", BN, widths[l]);
+  adi_mlp m = new (std::nothrow) adi_mlp_s();
+  if (!m) return fail(ADI_ENOMEM, "host allocation failed");
+  auto cleanup = [&](adi_status s) {
+    adi_mlp_destroy(m);
+    return s;
+  };
+  m->nl = nwidths - 1;
+  for (int l = 0; l < nwidths; ++l) m->width[l] = widths[l];
+  long off = 0;
+  for (int l = 0; l < m->nl; ++l) {
+    m->kin_pad[l] = l == 0 ? KPAD : widths[l];
+    m->woff[l] = off;
+    off += (long)widths[l] * widths[l + 1];
+    m->boff[l] = off;
+    off += widths[l + 1];
+  }
+  m->nparams = off;
+  hipError_t e = hipGetDevice(&m->device);
+  if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+  m->stream = (hipStream_t)hip_stream;
+  if (!m->stream) {
+    e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
+    m->own_stream = true;
+  }
+  adi_status st;
+  float** f32[] = {&m->P, &m->Gr, &m->Mm, &m->Vv};
+  for (float** p : f32)
+    if ((st = dev_alloc((void**)p, 4 * m->nparams, m->stream)) != ADI_OK) return cleanup(st);
+  for (int l = 0; l < m->nl; ++l) {
+    const long n = (long)m->kin_pad[l] * widths[l + 1];
+    if ((st = dev_alloc((void**)&m->Wb[l], 2 * n, m->stream)) != ADI_OK) return cleanup(st);
+    if ((st = dev_alloc((void**)&m->Wtb[l], 2 * n, m->stream)) != ADI_OK) return cleanup(st);
+  }
+  if ((st = dev_alloc((void**)&m->shift, 4 * KPAD, m->stream)) != ADI_OK) return cleanup(st);
+  if ((st = dev_alloc((void**)&m->scale, 4 * KPAD, m->stream)) != ADI_OK) return cleanup(st);
+  if ((st = dev_alloc((void**)&m->loss, 256, m->stream)) != ADI_OK) return cleanup(st);
+  // He-normal weights, zero biases (host generator, seeded)
+  std::vector<float> h(m->nparams, 0.0f);
+  std::mt19937_64 rng(seed);
+  for (int l = 0; l < m->nl; ++l) {
+    std::normal_distribution<double> nd(0.0, std::sqrt(2.0 / widths[l]));
+    for (long i = 0; i < (long)widths[l] * widths[l + 1]; ++i) h[m->woff[l] + i] = (float)nd(rng);
+  }
+  std::vector<float> one(KPAD, 1.0f);
+  e = hipMemcpyAsync(m->P, h.data(), 4 * m->nparams, hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->scale, one.data(), 4 * KPAD, hipMemcpyHostToDevice, m->stream);
+  if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "upload: %s", hipGetErrorString(e)));
+  if ((st = refresh_weights(m)) != ADI_OK) return cleanup(st);
+  e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "sync: %s", hipGetErrorString(e)));
+  *out = m;
+  return ADI_OK;
+}
+
+adi_status adi_mlp_num_params(adi_mlp m, int64_t* n) {
+  ADI_TRY(mlp_handle(m));
+  if (!n) return fail(ADI_EINVAL, "null output");
+  *n = m->nparams;
+  return ADI_OK;
+}
+
+adi_status adi_mlp_set_scaling(adi_mlp m, const float* shift, const float* scale) {
+  ADI_TRY(mlp_handle(m));
+  if (!shift || !scale) return fail(ADI_EINVAL, "null scaling array");
+  std::vector<float> s(KPAD, 0.0f), c(KPAD, 1.0f);
+  for (int i = 0; i < m->width[0]; ++i) {
+    if (!is_fin(shift[i]) || !is_fin(scale[i])) return fail(ADI_ENONFINITE, "scaling %d is not finite", i);
+    s[i] = shift[i];
+    c[i] = scale[i];
+  }
+  ADI_HIP(hipMemcpyAsync(m->shift, s.data(), 4 * KPAD, hipMemcpyHostToDevice, m->stream));
+  ADI_HIP(hipMemcpyAsync(m->scale, c.data(), 4 * KPAD, hipMemcpyHostToDevice, m->stream));
+  ADI_HIP(hipStreamSynchronize(m->stream));
+  return ADI_OK;
+}
+
+adi_status adi_mlp_get_params(adi_mlp m, float* host_out, int64_t count) {
+  ADI_TRY(mlp_handle(m));
+  if (!host_out || count != m->nparams) return fail(ADI_EINVAL, "need %ld parameters", m->nparams);
+  ADI_HIP(hipMemcpyAsync(host_out, m->P, 4 * m->nparams, hipMemcpyDeviceToHost, m->stream));
+  ADI_HIP(hipStreamSynchronize(m->stream));
+  return ADI_OK;
+}
+
+adi_status adi_mlp_set_params(adi_mlp m, const float* host_in, int64_t count) {
+  ADI_TRY(mlp_handle(m));
+  if (!host_in || count != m->nparams) return fail(ADI_EINVAL, "need %ld parameters", m->nparams);
+  for (long i = 0; i < m->nparams; ++i)
+    if (!is_fin(host_in[i])) return fail(ADI_ENONFINITE, "parameter %ld is not finite", i);
+  ADI_HIP(hipMemcpyAsync(m->P, host_in, 4 * m->nparams, hipMemcpyHostToDevice, m->stream));
+  ADI_TRY(refresh_weights(m));
+  ADI_HIP(hipStreamSynchronize(m->stream));
+  m->step = 0;
+  ADI_HIP(hipMemsetAsync(m->Mm, 0, 4 * m->nparams, m->stream));
+  ADI_HIP(hipMemsetAsync(m->Vv, 0, 4 * m->nparams, m->stream));
+  ADI_HIP(hipStreamSynchronize(m->stream));
+  return ADI_OK;
+}
+
+adi_status adi_mlp_forward(adi_mlp m, const float* dev_x, int64_t batch, float* dev_y) {
+  ADI_TRY(mlp_handle(m));
+  if (!dev_x || !dev_y) return fail(ADI_EINVAL, "null device buffer");
+  ADI_TRY(check_batch(m, batch));
+  ADI_TRY(ensure_acts(m, batch));
+  ADI_TRY(forward(m, dev_x, batch));
+  ADI_HIP(hipMemcpyAsync(dev_y, m->Y, 4 * batch * m->width[m->nl], hipMemcpyDeviceToDevice, m->stream));
+  return ADI_OK;
+}
+
+adi_status adi_mlp_gradients(adi_mlp m, const float* dev_x, const float* dev_t, int64_t batch, float* host_grads,
+                             float* loss_out) {
+  ADI_TRY(mlp_handle(m));
+  if (!dev_x || !dev_t) return fail(ADI_EINVAL, "null device buffer");
+  ADI_TRY(check_batch(m, batch));
+  ADI_TRY(ensure_acts(m, batch));
+  ADI_TRY(forward(m, dev_x, batch));
+  ADI_TRY(backward(m, dev_t, batch));
+  if (host_grads) ADI_HIP(hipMemcpyAsync(host_grads, m->Gr, 4 * m->nparams, hipMemcpyDeviceToHost, m->stream));
+  if (loss_out) ADI_HIP(hipMemcpyAsync(loss_out, m->loss, 4, hipMemcpyDeviceToHost, m->stream));
+  ADI_HIP(hipStreamSynchronize(m->stream));
+  return ADI_OK;
+}
+
+adi_status adi_mlp_train_step(adi_mlp m, const float* dev_x, const float* dev_t, int64_t batch, float lr,
+                              float* loss_out) {
+  ADI_TRY(mlp_handle(m));
+  if (!dev_x || !dev_t) return fail(ADI_EINVAL, "null device buffer");
+  if (!(lr >= 0.0f) || !is_fin(lr)) return fail(ADI_EINVAL, "learning rate must be >= 0");
+  ADI_TRY(check_batch(m, batch));
+  ADI_TRY(ensure_acts(m, batch));
+  ADI_TRY(forward(m, dev_x, batch));
+  ADI_TRY(backward(m, dev_t, batch));
+  m->step += 1;
+  const float c1 = 1.0f - std::pow(m->b1, (float)m->step), c2 = 1.0f - std::pow(m->b2, (float)m->step);
+  hipLaunchKernelGGL(k_adam, dim3((int)std::min<long>((m->nparams + 255) / 256, 2048)), dim3(256), 0, m->stream,
+                     m->P, m->Gr, m->Mm, m->Vv, m->nparams, lr, m->b1, m->b2, m->eps, c1, c2);
+  ADI_CHECK_LAUNCH();
+  ADI_TRY(refresh_weights(m));
+  if (loss_out) {
+    ADI_HIP(hipMemcpyAsync(loss_out, m->loss, 4, hipMemcpyDeviceToHost, m->stream));
+    ADI_HIP(hipStreamSynchronize(m->stream));
+  }
+  return ADI_OK;
+}
+
+void adi_mlp_destroy(adi_mlp m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  free_acts(m);
+  void* b[] = {m->P, m->Gr, m->Mm, m->Vv, m->shift, m->scale, m->part, m->loss};
+  for (void* p : b) dev_free(p);
+  for (int l = 0; l < MAX_LAYERS; ++l) {
+    dev_free(m->Wb[l]);
+    dev_free(m->Wtb[l]);
+  }
+  if (m->own_stream) (void)hipStreamDestroy(m->stream);
+  delete m;
+}
+
+}  // extern "C"

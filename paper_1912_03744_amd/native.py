@@ -92,11 +92,20 @@ _SIGS = {
     "adi_batch_read_field": [_vp, ctypes.c_int32, _dp, ctypes.c_size_t],
     "adi_batch_info": [_vp, ctypes.POINTER(ctypes.c_int64), _i32p, _i32p],
     "adi_batch_destroy": [_vp],
+    "adi_mlp_create": [_i32p, ctypes.c_int32, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)],
+    "adi_mlp_num_params": [_vp, ctypes.POINTER(ctypes.c_int64)],
+    "adi_mlp_set_scaling": [_vp, _fp, _fp],
+    "adi_mlp_get_params": [_vp, _fp, ctypes.c_int64],
+    "adi_mlp_set_params": [_vp, _fp, ctypes.c_int64],
+    "adi_mlp_forward": [_vp, _vp, ctypes.c_int64, _vp],
+    "adi_mlp_gradients": [_vp, _vp, _vp, ctypes.c_int64, _fp, _fp],
+    "adi_mlp_train_step": [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _fp],
+    "adi_mlp_destroy": [_vp],
     "adi_status_string": [ctypes.c_int],
     "adi_last_error": [],
     "adi_version": [],
 }
-_RESTYPE = {"adi_destroy": None, "adi_batch_destroy": None, "adi_status_string": ctypes.c_char_p,
+_RESTYPE = {"adi_destroy": None, "adi_batch_destroy": None, "adi_mlp_destroy": None, "adi_status_string": ctypes.c_char_p,
             "adi_last_error": ctypes.c_char_p, "adi_version": ctypes.c_char_p}
 
 _LIB = None
@@ -306,6 +315,78 @@ class Batch:
         tc, ns, wg = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         check(lib().adi_batch_info(self._h, ctypes.byref(tc), ctypes.byref(ns), ctypes.byref(wg)))
         return {"total_cells": tc.value, "nsnap": ns.value, "workgroups": wg.value}
+
+
+def _f32(a, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+class MLP:
+    """The surrogate network (adi_mlp_*).  Inputs/targets are torch cuda
+    float32 tensors (device memory); parameters move as numpy float32."""
+
+    def __init__(self, widths, seed=0, stream=None):
+        w = (ctypes.c_int32 * len(widths))(*[int(x) for x in widths])
+        h = _vp()
+        st = stream if stream is not None else current_stream()
+        check(lib().adi_mlp_create(w, len(widths), int(seed), st, ctypes.byref(h)))
+        self._h = h
+        self.widths = [int(x) for x in widths]
+        n = ctypes.c_int64()
+        check(lib().adi_mlp_num_params(self._h, ctypes.byref(n)))
+        self.nparams = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().adi_mlp_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_scaling(self, shift, scale):
+        n = self.widths[0]
+        a, b = _f32(shift, n), _f32(scale, n)
+        check(lib().adi_mlp_set_scaling(self._h, a.ctypes.data_as(_fp), b.ctypes.data_as(_fp)))
+
+    def params(self):
+        out = np.empty(self.nparams, dtype=np.float32)
+        check(lib().adi_mlp_get_params(self._h, out.ctypes.data_as(_fp), self.nparams))
+        return out
+
+    def set_params(self, p):
+        a = _f32(p, self.nparams)
+        check(lib().adi_mlp_set_params(self._h, a.ctypes.data_as(_fp), self.nparams))
+
+    def unflatten(self, flat):
+        """[(W_l, b_l)] views of a flat parameter vector."""
+        out, o = [], 0
+        for a, b in zip(self.widths[:-1], self.widths[1:]):
+            W = flat[o:o + a * b].reshape(a, b)
+            o += a * b
+            out.append((W, flat[o:o + b]))
+            o += b
+        return out
+
+    def forward(self, x, y):
+        """x, y: contiguous torch float32 cuda tensors [B, n_in] / [B, n_out]."""
+        check(lib().adi_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                    ctypes.c_void_p(y.data_ptr())))
+
+    def gradients(self, x, t):
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = ctypes.c_float()
+        check(lib().adi_mlp_gradients(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                      int(x.shape[0]), g.ctypes.data_as(_fp), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, t, lr, want_loss=False):
+        loss = ctypes.c_float()
+        check(lib().adi_mlp_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                       int(x.shape[0]), float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
 
 
 def launch_shapes():
