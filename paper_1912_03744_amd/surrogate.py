@@ -1,0 +1,394 @@
+"""Learned surrogate of the terminal-face temperature profile, and the
+surrogate-screened design sweep.
+
+Every numerical step runs in libadi's kernels: labels come from the batched
+FP64 ADI solver (adi_batch_*), the network is trained and evaluated by the
+bf16 matrix-core kernels (adi_mlp_*).  This module only arranges data (torch
+tensors as device memory), schedules and bookkeeping.
+
+Inputs (12 features): log10 k of the five regions, heater source Q,
+log10 h, r0, r1, r2, z0 and time t; each mapped affinely to [-1, 1] over the
+design box on the device (time enters as log10 t: heat reaches the terminal
+on a diffusion time scale, so log k and log t combine additively).  Output:
+64 values z_k = ln(y_k + Y_FLOOR) of the scaled outer terminal-face profile
+y_k = T_k / (Q t) (top row resampled at r_k = (k+0.5) rmax/64), decoded as
+exp(z) - Y_FLOOR.  rho c = 1, so y is in [0, 1] by the maximum principle
+(Q >= 0, T0 = T_inf = 0); the logarithm makes the squared loss a
+relative-error loss across the many decades the terminal temperature spans,
+and the floor maps a terminal that has not yet warmed to ~0.
+Relative errors are measured against max(max_k |T_k|, Y_FLOOR Q t), since
+early on the terminal face has not yet warmed and its temperature is ~0.
+
+Gate (when the surrogate's answer is kept): the design lies in the training
+box, every predicted y_k lies in [0, 1], and the two ensemble members
+disagree by at most delta (max_k |y1 - y2| / max_k |ybar|), with delta
+calibrated on validation solves so that accepted designs stayed within the
+target relative error.  Rejected designs are re-solved by the FP64 solver.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import native
+from . import workloads as W
+
+# design box: 5 log10 k, Q, log10 h, r0, r1, r2, z0 (as drawn by workloads.draw_design)
+BOX_LO = np.array([-2, -2, -2, -2, -2, 0.5, -2, 1.5, 2.0, 2.5, 6.0], dtype=np.float64)
+BOX_HI = np.array([1, 1, 1, 1, 1, 2.0, 0, 2.5, 4.0, 5.5, 9.0], dtype=np.float64)
+LOGT_LO, LOGT_HI = -1.0, math.log10(2.0)
+WIDTHS = [12, 256, 256, 256, 256, 64]
+LABEL_GRID = (128, 320)
+NPTS = 64
+Y_FLOOR = 1e-6
+
+
+def pipeline_stream():
+    """A torch stream (default priority) to run the pipeline on: torch's
+    tensor work and the library's kernels are then ordered on one stream."""
+    import torch
+    return torch.cuda.Stream()
+
+
+def design_for_seed(seed: int) -> np.ndarray:
+    d = W.draw_design(np.random.Generator(np.random.PCG64(seed)))
+    return np.concatenate([d["logk"], [d["q"], d["logh"], d["r0"], d["r1"], d["r2"], d["z0"]]])
+
+
+def designs_for_seeds(seeds) -> np.ndarray:
+    return np.stack([design_for_seed(int(s)) for s in seeds])
+
+
+def feature_scaling():
+    lo = np.concatenate([BOX_LO, [LOGT_LO]])
+    hi = np.concatenate([BOX_HI, [LOGT_HI]])
+    return (lo + hi) / 2, 2.0 / (hi - lo)
+
+
+def features(D: np.ndarray, t) -> np.ndarray:
+    """Network inputs for designs D at times t (scalar or per row)."""
+    t = np.broadcast_to(np.asarray(t, dtype=np.float64), (len(D),))
+    return np.concatenate([D, np.log10(t)[:, None]], axis=1).astype(np.float32)
+
+
+def in_box(D: np.ndarray) -> np.ndarray:
+    return np.all((D >= BOX_LO - 1e-12) & (D <= BOX_HI + 1e-12), axis=1)
+
+
+def solve_profiles(D: np.ndarray, nsteps=2000, dt=1e-3, snap_every=100, grid=LABEL_GRID, chunk=4096,
+                   log=None, launch=(2, 8, 1)):
+    """Terminal-face profiles of designs D (rows of 11 parameters) from the
+    batched FP64 solver: [n, nsteps // snap_every, 64]."""
+    n = len(D)
+    nsnap = nsteps // snap_every if snap_every else 0
+    out = np.empty((n, max(nsnap, 1), NPTS))
+    for a in range(0, n, chunk):
+        specs = [W.design_spec(W.design_from_row(x), *grid, dt=dt, nsteps=nsteps) for x in D[a:a + chunk]]
+        b = native.Batch(specs)
+        b.set_launch(*launch)
+        t0 = time.perf_counter()
+        b.step(dt, nsteps, snapshot_every=snap_every if snap_every else nsteps, npts=NPTS)
+        prof = b.profiles()
+        if log:
+            log("solved %d designs (%dx%d, %d steps) in %.2f s" % (len(specs), grid[0], grid[1], nsteps,
+                                                                 time.perf_counter() - t0))
+        out[a:a + len(specs)] = prof
+        b.close()
+    return out
+
+
+def make_pairs(D: np.ndarray, prof: np.ndarray, snap_dt: float):
+    """(X, Y): one row per (design, snapshot); Y = scaled profile
+    y = T / (Q t) (float64, for judging); the network target is encode(Y)."""
+    n, nsnap, _ = prof.shape
+    t = snap_dt * (np.arange(nsnap) + 1)
+    X = features(np.repeat(D, nsnap, axis=0), np.tile(t, n))
+    Q = np.repeat(D[:, 5], nsnap)
+    Y = prof.reshape(n * nsnap, -1) / (Q * np.tile(t, n))[:, None]
+    return X, Y
+
+
+def encode(y):
+    return np.log(np.maximum(y, 0.0) + Y_FLOOR).astype(np.float32)
+
+
+def decode(z):
+    return np.exp(z.astype(np.float64)) - Y_FLOOR
+
+
+@dataclass
+class Surrogate:
+    nets: list
+    delta: float = math.inf
+    history: list = field(default_factory=list)
+
+    def predict(self, X: np.ndarray, chunk=65536):
+        """Ensemble predictions [members, n, 64] (numpy) for feature rows X."""
+        import torch
+        n = len(X)
+        out = np.empty((len(self.nets), n, NPTS), dtype=np.float32)
+        for a in range(0, n, chunk):
+            xb = X[a:a + chunk]
+            m = len(xb)
+            pad = (-m) % 64
+            xt = torch.zeros(m + pad, X.shape[1], device="cuda")
+            xt[:m] = torch.from_numpy(np.ascontiguousarray(xb, dtype=np.float32)).cuda()
+            yt = torch.empty(m + pad, NPTS, device="cuda")
+            for i, net in enumerate(self.nets):
+                net.forward(xt, yt)
+                torch.cuda.synchronize()
+                out[i, a:a + m] = yt[:m].cpu().numpy()
+        return out
+
+    @staticmethod
+    def disagreement(P: np.ndarray) -> np.ndarray:
+        """Relative disagreement of the first and last members on the
+        scaled profile (network outputs are logarithms)."""
+        y0, y1 = decode(P[0]), decode(P[-1])
+        ybar = 0.5 * (y0 + y1)
+        return np.max(np.abs(y0 - y1), axis=1) / np.maximum(np.max(ybar, axis=1), Y_FLOOR)
+
+    @staticmethod
+    def profile(P: np.ndarray) -> np.ndarray:
+        """Ensemble-mean scaled profile y."""
+        return decode(P).mean(axis=0)
+
+    def gate(self, D: np.ndarray, P: np.ndarray) -> np.ndarray:
+        """True where the surrogate's answer is kept."""
+        y = self.profile(P)
+        ok = in_box(D[:, :11])
+        ok &= np.all(y <= 1.0 + 1e-3, axis=1)  # maximum principle (y >= 0 holds by construction)
+        ok &= self.disagreement(P) <= self.delta
+        return ok
+
+
+def rel_profile_error(pred_y: np.ndarray, true_y: np.ndarray) -> np.ndarray:
+    """max_k |pred - true| / max(max_k |true|, Y_FLOOR), on scaled profiles
+    (the same number as on temperatures, the scale Q t cancelling)."""
+    return np.max(np.abs(pred_y - true_y), axis=-1) / np.maximum(np.max(np.abs(true_y), axis=-1), Y_FLOOR)
+
+
+def train(X: np.ndarray, Y: np.ndarray, members=2, epochs=30, batch=4096, lr=2e-3, lr_end=2e-5, seed=0,
+          log=None, Xval=None, Yval=None):
+    """Train an ensemble (different initialisations and data orders)."""
+    import torch
+    shift, scale = feature_scaling()
+    xt = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    yt = torch.from_numpy(np.ascontiguousarray(encode(Y))).cuda()
+    n = (len(X) // batch) * batch
+    nets, hist = [], []
+    steps = epochs * (n // batch)
+    for mi in range(members):
+        net = native.MLP(WIDTHS, seed=seed + 1000 * mi)
+        net.set_scaling(shift, scale)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed + 17 * mi)
+        it = 0
+        t0 = time.perf_counter()
+        for ep in range(epochs):
+            perm = torch.randperm(len(X), device="cuda", generator=g)[:n]
+            xs, ys = xt[perm].contiguous(), yt[perm].contiguous()
+            last = None
+            for b in range(n // batch):
+                frac = it / max(1, steps - 1)
+                cur = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac))
+                want = b == n // batch - 1
+                loss = net.train_step(xs[b * batch:(b + 1) * batch], ys[b * batch:(b + 1) * batch], cur,
+                                      want_loss=want)
+                if want:
+                    last = loss
+                it += 1
+            hist.append((mi, ep, last))
+            if log and (ep % 5 == 4 or ep == epochs - 1):
+                log("member %d epoch %d loss %.3e (%.1f s)" % (mi, ep + 1, last, time.perf_counter() - t0))
+        nets.append(net)
+    return Surrogate(nets=nets, history=hist)
+
+
+def calibrate(sur: Surrogate, Xv: np.ndarray, Yv: np.ndarray, target=1e-3, also=(1e-2,)):
+    """Largest ensemble-disagreement threshold such that every validation
+    pair accepted under it has relative profile error <= target (set as the
+    gate); the thresholds for the `also` targets are reported beside it."""
+    P = sur.predict(Xv)
+    err = rel_profile_error(Surrogate.profile(P), Yv)
+    dis = Surrogate.disagreement(P)
+    order = np.argsort(dis)
+
+    def thresh(tg):
+        bad = np.nonzero(err[order] > tg)[0]
+        k = int(bad[0]) if len(bad) else len(order)
+        return (float(dis[order[k - 1]]) if k > 0 else 0.0), k / len(order)
+
+    sur.delta, rate = thresh(target)
+    out = {"target": target, "delta": sur.delta, "val_accept_rate": rate, "val_median_err": float(np.median(err)),
+           "val_p99_err": float(np.quantile(err, 0.99)), "val_max_err": float(err.max())}
+    for tg in also:
+        d, r = thresh(tg)
+        out["delta_at_%g" % tg] = d
+        out["val_accept_rate_at_%g" % tg] = r
+    return out
+
+
+def plain_solver_seconds(D: np.ndarray, nsteps, dt, grid=LABEL_GRID):
+    """Wall time per design of the plain single-instance GPU solver (one
+    problem at a time, captured step graphs), for the no-surrogate baseline."""
+    import torch
+    ts = []
+    for x in D:
+        s = W.design_spec(W.design_from_row(x), *grid, dt=dt, nsteps=nsteps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = native.Problem.from_spec(s)
+        p.set_graph_steps(100)
+        p.step(dt, nsteps)
+        p.profile(0, NPTS)
+        ts.append(time.perf_counter() - t0)
+        p.close()
+    return float(np.median(ts)), ts
+
+
+def spearman(a, b):
+    ra = np.argsort(np.argsort(a))
+    rb = np.argsort(np.argsort(b))
+    return float(np.corrcoef(ra, rb)[0, 1])
+
+
+def run(n_train=32768, n_val=2048, n_test=4096, n_sweep=1 << 20, top_frac=0.01, epochs=30, n_recall=16384,
+        n_plain=64, log=print, seed=0):
+    """Train the surrogate on batched FP64 solves, calibrate the gate, judge
+    it on held-out solves, then run the screened sweep against the solver."""
+    import torch
+    with torch.cuda.stream(pipeline_stream()):
+        return _run(n_train, n_val, n_test, n_sweep, top_frac, epochs, n_recall, n_plain, log, seed)
+
+
+def _run(n_train, n_val, n_test, n_sweep, top_frac, epochs, n_recall, n_plain, log, seed):
+    import torch
+    res = {"widths": WIDTHS, "label_grid": list(LABEL_GRID)}
+    t_all = time.perf_counter()
+    # labels: 2000 steps of dt = 1e-3, profiles at t = 0.1, 0.2, ..., 2.0
+    Dtr = designs_for_seeds(range(n_train))
+    Dva = designs_for_seeds(range(500_000_000, 500_000_000 + n_val))
+    Dte = designs_for_seeds(range(1_000_000_000, 1_000_000_000 + n_test))
+    t0 = time.perf_counter()
+    Ptr = solve_profiles(Dtr, log=log)
+    Pva = solve_profiles(Dva, log=log)
+    Pte = solve_profiles(Dte, log=log)
+    res["label_seconds"] = time.perf_counter() - t0
+    res["label_cell_updates"] = float((n_train + n_val + n_test) * LABEL_GRID[0] * LABEL_GRID[1] * 2000)
+    Xtr, Ytr = make_pairs(Dtr, Ptr, 0.1)
+    Xva, Yva = make_pairs(Dva, Pva, 0.1)
+    Xte, Yte = make_pairs(Dte, Pte, 0.1)
+    t0 = time.perf_counter()
+    sur = train(Xtr, Ytr, epochs=epochs, log=log, seed=seed)
+    torch.cuda.synchronize()
+    res["train_seconds"] = time.perf_counter() - t0
+    res["train_pairs"] = len(Xtr)
+    res["calibration"] = calibrate(sur, Xva, Yva)
+    log("calibration %s" % res["calibration"])
+    # held-out judgement, every snapshot time
+    P = sur.predict(Xte)
+    err = rel_profile_error(Surrogate.profile(P), Yte)
+    ok = sur.gate(Xte[:, :11].astype(np.float64), P)
+    d_main = sur.delta
+    sur.delta = res["calibration"]["delta_at_0.01"]
+    ok2 = sur.gate(Xte[:, :11].astype(np.float64), P)
+    sur.delta = d_main
+    res["heldout"] = {"pairs": int(len(err)), "median_err": float(np.median(err)),
+                      "p99_err": float(np.quantile(err, 0.99)), "max_err": float(err.max()),
+                      "gate_pass_rate": float(ok.mean()),
+                      "max_err_passed": float(err[ok].max()) if ok.any() else None,
+                      "max_err_after_fallback": float(err[ok].max()) if ok.any() else 0.0,
+                      "frac_err_le_1e-3": float(np.mean(err <= 1e-3)),
+                      "frac_err_le_1e-2": float(np.mean(err <= 1e-2)),
+                      "median_err_at_t2": float(np.median(err.reshape(-1, 20)[:, -1])),
+                      "gate_pass_rate_at_1e-2": float(ok2.mean()),
+                      "max_err_passed_at_1e-2": float(err[ok2].max()) if ok2.any() else None}
+    log("held-out %s" % res["heldout"])
+
+    # screened sweep: peak terminal temperature at t = 2
+    rng_t = time.perf_counter()
+    Dsw = W.design_matrix(n_sweep, seed=1)
+    res["sweep_draw_seconds"] = time.perf_counter() - rng_t
+    Xsw = features(Dsw, 2.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Psw = sur.predict(Xsw)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    ybar = Surrogate.profile(Psw)
+    peak_pred = ybar.max(axis=1) * Dsw[:, 5] * 2.0
+    gate_ok = sur.gate(Dsw, Psw)
+    k = int(round(top_frac * n_sweep))
+    top = np.argsort(-peak_pred)[:k]
+    # the selected designs plus every selected gate failure go to the solver
+    t0 = time.perf_counter()
+    Ptop = solve_profiles(Dsw[top], nsteps=5000, dt=4e-4, snap_every=5000, log=log)[:, 0]
+    t_res = time.perf_counter() - t0
+    true_peak = Ptop.max(axis=1)
+    sel_err = rel_profile_error(ybar[top], Ptop / (Dsw[top, 5] * 2.0)[:, None])
+    res["sweep"] = {"designs": n_sweep, "selected": k, "inference_seconds": t_inf,
+                    "resolve_seconds": t_res, "gate_pass_rate": float(gate_ok.mean()),
+                    "selected_gate_pass_rate": float(gate_ok[top].mean()),
+                    "spearman_selected": spearman(peak_pred[top], true_peak),
+                    "max_rel_err_selected": float(sel_err.max()),
+                    "median_rel_err_selected": float(np.median(sel_err))}
+    t_screened = t_inf + t_res
+    # recall@1% on a fully solved subset
+    sub = np.arange(n_recall)
+    t0 = time.perf_counter()
+    Psub = solve_profiles(Dsw[sub], nsteps=5000, dt=4e-4, snap_every=5000, log=log)[:, 0]
+    t_batched = time.perf_counter() - t0
+    truth = Psub.max(axis=1)
+    kk = max(1, int(round(top_frac * n_recall)))
+    true_top = set(np.argsort(-truth)[:kk])
+    pred_top = set(np.argsort(-peak_pred[sub])[:kk])
+    res["sweep"]["recall_at_top"] = len(true_top & pred_top) / kk
+    res["sweep"]["batched_solver_seconds_per_design"] = t_batched / n_recall
+    # plain per-instance solver, extrapolated
+    t_plain, _ = plain_solver_seconds(Dsw[:n_plain], 5000, 4e-4)
+    res["sweep"]["plain_solver_seconds_per_design"] = t_plain
+    res["sweep"]["designs_per_s_screened"] = n_sweep / t_screened
+    res["sweep"]["designs_per_s_plain"] = 1.0 / t_plain
+    res["sweep"]["designs_per_s_batched_only"] = n_recall / t_batched
+    res["sweep"]["gain_vs_plain"] = (n_sweep / t_screened) * t_plain
+    res["sweep"]["gain_vs_batched_only"] = (n_sweep / t_screened) / (n_recall / t_batched)
+    log("sweep %s" % res["sweep"])
+    res["total_seconds"] = time.perf_counter() - t_all
+    return res
+
+
+def main():
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="train the surrogate and run the screened design sweep")
+    ap.add_argument("--n-train", type=int, default=32768)
+    ap.add_argument("--n-val", type=int, default=2048)
+    ap.add_argument("--n-test", type=int, default=4096)
+    ap.add_argument("--n-sweep", type=int, default=1 << 20)
+    ap.add_argument("--n-recall", type=int, default=16384)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--n-plain", type=int, default=64)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    res = run(n_train=a.n_train, n_val=a.n_val, n_test=a.n_test, n_sweep=a.n_sweep, epochs=a.epochs,
+              n_recall=a.n_recall, n_plain=a.n_plain, log=log)
+    txt = json.dumps(res, indent=1)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+    print(txt)
+
+
+if __name__ == "__main__":
+    main()
