@@ -17,7 +17,11 @@ Prints one JSON line:
               the kernel runs on
   cpu_baseline  the CPU FP64 oracle timed on a bounded sample of the same
               workload on this host
-Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 200]
+  batch       secondary figure: the ragged design batch (4096 seeded
+              instances of 64x160 ... 192x480 cells, 2000 PR steps of 1e-3)
+              in one persistent launch, autotuned; cell-updates/s and the
+              kernel's algorithmic bandwidth (32 B per active cell per step)
+Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 200] [--no-batch]
 """
 from __future__ import annotations
 
@@ -75,6 +79,36 @@ def cpu_baseline(spec, steps):
                       % (steps, spec.nr, spec.nz), "seconds": round(dt, 3)}
 
 
+def batch_leg(n, steps, tune=True):
+    """The ragged design batch: one timed adi_batch_step call over all
+    instances from their initial fields (events on the batch's stream)."""
+    from paper_1912_03744_amd import autotune, native
+    from paper_1912_03744_amd import workloads as W
+    specs = W.ragged_batch(n, master_seed=0, scheme="pr", dt=1e-3, nsteps=steps)
+    dt = specs[0].dt
+    b = native.Batch(specs, scheme="pr")
+    if tune:
+        t0 = time.perf_counter()
+        tuned = autotune.apply_batch(b, dt, "pr")
+        print("bench: batch autotune %.1f s -> %s" % (time.perf_counter() - t0, tuned["shape"]),
+              file=sys.stderr, flush=True)
+    b.time(dt, 20, 1)  # warm-up (allocates the workgroup scratch)
+    ms = b.time(dt, steps, 1)
+    active, cells = b.active_cells(), b.cells()
+    sec = ms * 1e-3
+    achieved = 2 * BYTES_PER_CELL_HALF_STEP * active * steps / sec / 1e9
+    shape = b.info()
+    out = {"workload": "ragged design batch: %d instances, sizes U{64x160, 96x240, 128x320, 192x480}, "
+                       "master seed 0, Peaceman-Rachford, dt=%g, %d steps, one persistent launch" % (n, dt, steps),
+           "value": active * steps / sec, "unit": "cell-updates/s", "cups_all_cells": cells * steps / sec,
+           "seconds": sec, "designs_per_s": n / sec, "active_cells": active, "cells": cells,
+           "workgroups": shape["workgroups"],
+           "roofline": {"bound": "hbm", "kernel": "batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +119,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-n", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -162,6 +199,11 @@ def main():
         "cups_all_cells": cells * args.steps / wall,
         "energy_residual": rep["residual"],
     }
+    p.close()
+    if not args.no_batch:
+        out["batch"] = batch_leg(args.batch_n, args.batch_steps, tune=not args.no_tune)
+        print("bench: batch %.3f s, %.3e cell-updates/s" % (out["batch"]["seconds"], out["batch"]["value"]),
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
     print(json.dumps(out), flush=True)

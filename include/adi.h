@@ -222,6 +222,15 @@ adi_status adi_batch_read_field(adi_batch b, int32_t i, double* host_out, size_t
  * persistent workgroups launched. */
 adi_status adi_batch_info(adi_batch b, int64_t* total_cells, int32_t* nsnap, int32_t* workgroups);
 
+/* Cells inside the domain (not masked) summed over all instances. */
+adi_status adi_batch_active_cells(adi_batch b, int64_t* active);
+
+/* Run adi_batch_step(b, dt, nsteps, 0, 64) reps times back to back,
+ * bracketed by HIP events on the batch's stream, and return the mean
+ * milliseconds per call (launch shape as set; fields end as after one call).
+ * Synchronises.  Used by the autotuner and the benchmark. */
+adi_status adi_batch_time(adi_batch b, double dt, int64_t nsteps, int32_t reps, float* ms_out);
+
 void adi_batch_destroy(adi_batch b);
 
 /* ---------------------------------------------------- learned surrogate -- */

@@ -1,11 +1,14 @@
-"""Launch-shape autotuner for the line-solve sweeps.
+"""Launch-shape autotuner for the line-solve sweeps and the ragged batch.
 
-For each sweep direction of a problem it times every compiled launch shape
-(cells per chunk, lines per wave, waves per line, lines per lane, groups per
-workgroup) that covers the line length without too much padding, using
-adi_time_sweeps (HIP events on the problem's stream), and keeps the fastest.  Results are cached in a
-JSON file keyed by GPU architecture, grid size and scheme: $ADI_AUTOTUNE_CACHE
-or ~/.cache/adi_autotune.json.
+Single problems: for each sweep direction it times every compiled launch
+shape (cells per chunk, lines per wave, waves per line, lines per lane,
+groups per workgroup) that covers the line length without too much padding,
+using adi_time_sweeps (HIP events on the problem's stream), and keeps the
+fastest.  Ragged batches: it times the persistent batch kernel (lines per
+lane, waves per workgroup, resident workgroups per compute unit) on a short
+run of the batch itself with adi_batch_time.  Results are cached in a JSON
+file keyed by GPU architecture, problem size (or the batch's size mix) and
+scheme: $ADI_AUTOTUNE_CACHE or ~/.cache/adi_autotune.json.
 """
 from __future__ import annotations
 
@@ -102,6 +105,57 @@ def apply(problem, dt, scheme, retune=False, verbose=False, log=None):
     entry = {"r": {"shape": list(r["r"][0]), "ms": r["r"][1]},
              "z": {"shape": list(r["z"][0]), "ms": r["z"][1]},
              "seconds": time.time() - t0, "trials": len(r["trials"])}
+    db = _load()
+    db[k] = entry
+    _store(db)
+    return entry
+
+
+# compiled batch kernels: (lines per lane, waves per workgroup); resident
+# workgroups per compute unit is a launch parameter
+BATCH_KERNELS = ((1, 4), (2, 4), (1, 8), (2, 8))
+BATCH_BLOCKS_PER_CU = (1, 2, 4)
+
+
+def batch_key(batch, scheme):
+    mix = {}
+    for nr, nz in batch.shapes:
+        mix["%dx%d" % (nr, nz)] = mix.get("%dx%d" % (nr, nz), 0) + 1
+    return "%s/batch%d/%s/%s" % (_arch(), batch.n, ",".join("%s:%d" % kv for kv in sorted(mix.items())),
+                                  scheme)
+
+
+def tune_batch(batch, dt, nsteps=100, verbose=False, log=None):
+    """Time every batch launch shape on nsteps steps of the batch itself and
+    set the fastest.  Returns {"shape": (R, waves, blocks_per_cu), "ms": t,
+    "trials": [...]}."""
+    trials, best = [], None
+    for r, nw in BATCH_KERNELS:
+        for bpc in BATCH_BLOCKS_PER_CU:
+            batch.set_launch(r, nw, bpc)
+            batch.time(dt, nsteps, 1)  # first call allocates the workgroup scratch
+            t = batch.time(dt, nsteps, 1)
+            trials.append({"shape": (r, nw, bpc), "ms": t})
+            if verbose:
+                msg = "autotune batch shape %s: %.3f ms for %d steps" % ((r, nw, bpc), t, nsteps)
+                print(msg, flush=True) if log is None else log(msg)
+            if best is None or t < best[1]:
+                best = ((r, nw, bpc), t)
+    batch.set_launch(*best[0])
+    return {"shape": best[0], "ms": best[1], "trials": trials}
+
+
+def apply_batch(batch, dt, scheme, nsteps=100, retune=False, verbose=False, log=None):
+    """Set the cached best batch shape for this size mix, tuning on a miss."""
+    db = _load()
+    k = batch_key(batch, scheme)
+    if not retune and k in db:
+        batch.set_launch(*db[k]["shape"])
+        return db[k]
+    t0 = time.time()
+    r = tune_batch(batch, dt, nsteps, verbose=verbose, log=log)
+    entry = {"shape": list(r["shape"]), "ms": r["ms"], "steps": nsteps, "seconds": time.time() - t0,
+             "trials": len(r["trials"])}
     db = _load()
     db[k] = entry
     _store(db)

@@ -302,7 +302,8 @@ struct adi_batch_s {
   int* dorder = nullptr;
   int* queue = nullptr;
   double* T = nullptr;
-  long total_cells = 0, maxcells = 0;
+  long total_cells = 0, maxcells = 0;  // arena size (aligned), largest instance
+  long cells = 0, active = 0;           // cells, cells inside the domain
   double* prof = nullptr;
   long prof_cap = 0;  // doubles
   int nsnap = 0, npts = 64;
@@ -388,6 +389,16 @@ adi_status adi_create_batch(int32_t n, const adi_geometry* geoms, const adi_bc* 
     I.toff = off;
     off += ((long)g.nr * g.nz + 31) & ~31L;  // 256-byte aligned fields (16-byte vector stores)
     b->maxcells = std::max(b->maxcells, (long)g.nr * g.nz);
+    // cells outside the domain: columns with centre r >= r0 times rows with
+    // z0 <= centre z < zmax (centres evaluated as on the device)
+    long ncol = 0, nrow = 0;
+    for (int ii = 0; ii < g.nr; ++ii) ncol += (ii + 0.5) * g.rmax / g.nr >= g.r0;
+    for (int jj = 0; jj < g.nz; ++jj) {
+      const double zc = (jj + 0.5) * g.ztop / g.nz;
+      nrow += zc >= g.z0 && zc < g.zmax;
+    }
+    b->cells += (long)g.nr * g.nz;
+    b->active += (long)g.nr * g.nz - ncol * nrow;
   }
   b->total_cells = off;
   b->lay = make_layout(b->maxcells);
@@ -550,6 +561,33 @@ adi_status adi_batch_info(adi_batch b, int64_t* total_cells, int32_t* nsnap, int
   if (total_cells) *total_cells = b->total_cells;
   if (nsnap) *nsnap = b->nsnap;
   if (workgroups) *workgroups = b->nblocks;
+  return ADI_OK;
+}
+
+adi_status adi_batch_active_cells(adi_batch b, int64_t* active) {
+  ADI_TRY(batch_handle(b));
+  if (!active) return fail(ADI_EINVAL, "null output");
+  *active = b->active;
+  return ADI_OK;
+}
+
+adi_status adi_batch_time(adi_batch b, double dt, int64_t nsteps, int32_t reps, float* ms_out) {
+  ADI_TRY(batch_handle(b));
+  if (reps < 1) return fail(ADI_EINVAL, "reps must be >= 1");
+  if (!ms_out) return fail(ADI_EINVAL, "null output");
+  hipEvent_t ev[2];
+  for (auto& x : ev) ADI_HIP(hipEventCreate(&x));
+  adi_status st = ADI_OK;
+  (void)hipEventRecord(ev[0], b->stream);
+  for (int i = 0; i < reps && st == ADI_OK; ++i) st = adi_batch_step(b, dt, nsteps, 0, 64);
+  (void)hipEventRecord(ev[1], b->stream);
+  hipError_t e = hipEventSynchronize(ev[1]);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (st != ADI_OK) return st;
+  if (e != hipSuccess) return fail(ADI_EDEVICE, "event timing: %s", hipGetErrorString(e));
+  *ms_out = ms / reps;
   return ADI_OK;
 }
 

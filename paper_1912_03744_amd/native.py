@@ -91,6 +91,8 @@ _SIGS = {
     "adi_batch_read_profiles": [_vp, _dp, ctypes.c_size_t],
     "adi_batch_read_field": [_vp, ctypes.c_int32, _dp, ctypes.c_size_t],
     "adi_batch_info": [_vp, ctypes.POINTER(ctypes.c_int64), _i32p, _i32p],
+    "adi_batch_active_cells": [_vp, ctypes.POINTER(ctypes.c_int64)],
+    "adi_batch_time": [_vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)],
     "adi_batch_destroy": [_vp],
     "adi_mlp_create": [_i32p, ctypes.c_int32, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)],
     "adi_mlp_num_params": [_vp, ctypes.POINTER(ctypes.c_int64)],
@@ -174,6 +176,7 @@ class Problem:
         check(lib().adi_create_problem(ctypes.byref(g), ctypes.byref(bc), SCHEMES[scheme], st,
                                        ctypes.byref(h_)))
         self._h = h_
+        self._destroy = lib().adi_destroy
         self.scheme = scheme
 
     @classmethod
@@ -185,9 +188,12 @@ class Problem:
         return p
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().adi_destroy(self._h)
-            self._h = None
+        # the destroy function is looked up while the module is alive: at
+        # interpreter shutdown module globals may already be gone
+        h, destroy = getattr(self, "_h", None), getattr(self, "_destroy", None)
+        if h and destroy is not None:
+            destroy(h)
+        self._h = None
 
     __del__ = close
 
@@ -271,6 +277,7 @@ class Batch:
         st = stream if stream is not None else current_stream()
         check(lib().adi_create_batch(n, geoms, bcs, SCHEMES[scheme], st, ctypes.byref(h)))
         self._h = h
+        self._destroy = lib().adi_batch_destroy
         self.n = n
         self.shapes = [(int(s.nr), int(s.nz)) for s in specs]
         k = _f64([s.k for s in specs], 5 * n)
@@ -282,9 +289,12 @@ class Batch:
         self._nsnap, self._npts = 0, 64
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().adi_batch_destroy(self._h)
-            self._h = None
+        # the destroy function is looked up while the module is alive: at
+        # interpreter shutdown module globals may already be gone
+        h, destroy = getattr(self, "_h", None), getattr(self, "_destroy", None)
+        if h and destroy is not None:
+            destroy(h)
+        self._h = None
 
     __del__ = close
 
@@ -316,6 +326,21 @@ class Batch:
         check(lib().adi_batch_info(self._h, ctypes.byref(tc), ctypes.byref(ns), ctypes.byref(wg)))
         return {"total_cells": tc.value, "nsnap": ns.value, "workgroups": wg.value}
 
+    def active_cells(self):
+        a = ctypes.c_int64()
+        check(lib().adi_batch_active_cells(self._h, ctypes.byref(a)))
+        return a.value
+
+    def cells(self):
+        return sum(nr * nz for nr, nz in self.shapes)
+
+    def time(self, dt, nsteps, reps=1):
+        """Mean milliseconds of one adi_batch_step(dt, nsteps) call (HIP
+        events on the batch's stream)."""
+        ms = ctypes.c_float()
+        check(lib().adi_batch_time(self._h, float(dt), int(nsteps), int(reps), ctypes.byref(ms)))
+        return ms.value
+
 
 def _f32(a, n=None):
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
@@ -334,15 +359,19 @@ class MLP:
         st = stream if stream is not None else current_stream()
         check(lib().adi_mlp_create(w, len(widths), int(seed), st, ctypes.byref(h)))
         self._h = h
+        self._destroy = lib().adi_mlp_destroy
         self.widths = [int(x) for x in widths]
         n = ctypes.c_int64()
         check(lib().adi_mlp_num_params(self._h, ctypes.byref(n)))
         self.nparams = n.value
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().adi_mlp_destroy(self._h)
-            self._h = None
+        # the destroy function is looked up while the module is alive: at
+        # interpreter shutdown module globals may already be gone
+        h, destroy = getattr(self, "_h", None), getattr(self, "_destroy", None)
+        if h and destroy is not None:
+            destroy(h)
+        self._h = None
 
     __del__ = close
 

@@ -87,3 +87,45 @@ def test_batch_errors():
         b.set_launch(3, 4, 1)
     with pytest.raises(native.AdiError):
         b.step(-1.0, 10)
+
+
+def test_batch_active_cells_and_timing():
+    """The library's count of cells inside the domain equals the oracle's
+    region maps, and the timed entry point leaves the same fields as a plain
+    step call."""
+    from paper_1912_03744_amd import native
+    specs = W.ragged_batch(24, master_seed=5, nsteps=30)
+    b = native.Batch(specs)
+    want = sum(int(np.count_nonzero(oracle.Problem.from_spec(s).active())) for s in specs)
+    assert b.active_cells() == want
+    assert b.cells() == sum(s.nr * s.nz for s in specs)
+    b.step(1e-3, 30)
+    ref = [b.field(i) for i in (0, 7)]
+    ms = b.time(1e-3, 30, 2)
+    assert ms > 0.0
+    for i, r in zip((0, 7), ref):
+        assert np.array_equal(b.field(i), r)
+
+
+def test_batch_full_size_sampled(tmp_path, monkeypatch):
+    """The benchmark's batch: 4096 instances, 2000 steps, in the launch shape
+    the autotuner picks; one sampled instance per size class against the
+    oracle run alone (field and terminal-face profile at t = 1 and 2)."""
+    from paper_1912_03744_amd import autotune, native
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
+    specs = W.ragged_batch(4096, master_seed=0, scheme="pr", dt=1e-3, nsteps=2000)
+    b = native.Batch(specs, scheme="pr")
+    tuned = autotune.apply_batch(b, 1e-3, "pr", nsteps=50)
+    print("batch tuned shape %s" % (tuned["shape"],), flush=True)
+    b.step(1e-3, 2000, snapshot_every=1000, npts=64)
+    prof = b.profiles()
+    picks = []
+    for size in W.BATCH_SIZES:
+        picks.append(next(i for i, s in enumerate(specs) if (s.nr, s.nz) == size))
+    for i in picks:
+        s = specs[i]
+        print("batch full size: instance %d (%dx%d)" % (i, s.nr, s.nz), flush=True)
+        P, want = _oracle_run(s, 2000)
+        assert rel_inf(b.field(i), want, P.active()) <= TOL, (i, s.nr, s.nz)
+        wp = P.profile(want, 0, 64)
+        assert np.max(np.abs(prof[i, 1] - wp)) <= TOL * np.max(np.abs(wp))

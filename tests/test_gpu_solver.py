@@ -91,15 +91,19 @@ def test_launch_shapes_ragged(shape):
         pytest.skip("shape covers none of the line lengths")
 
 
-def test_production_full_size_short_run():
-    """1024 x 2560 at the production time step, in the default launch shape
-    of the benchmark: full-field parity after 4 steps (both schemes)."""
+def test_production_full_size_short_run(tmp_path, monkeypatch):
+    """1024 x 2560 at the production time step, in the launch shapes the
+    autotuner picks for the benchmark (and in the default shapes): full-field
+    parity after 4 steps (both schemes)."""
+    from paper_1912_03744_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
     for scheme in ("pr", "lod"):
         s = W.production(0, scheme=scheme)
-        _say("production full size %s" % scheme)
         P, want, _ = run_oracle(s, 4)
-        p, got = run_gpu(s, 4)
-        assert rel_inf(got, want, P.active()) <= TOL
+        for tune in (False, True):
+            _say("production full size %s tuned=%s" % (scheme, tune))
+            p, got = run_gpu(s, 4, tune=tune)
+            assert rel_inf(got, want, P.active()) <= TOL
 
 
 def test_production_energy_identity_long_run():
