@@ -143,8 +143,8 @@ def main():
     if not args.no_tune:
         t0 = time.perf_counter()
         tuned = autotune.apply(p, spec.dt, spec.scheme)
-        print("bench: autotune %.1f s -> r %s z %s" % (time.perf_counter() - t0, tuned["r"]["shape"],
-              tuned["z"]["shape"]), file=sys.stderr, flush=True)
+        print("bench: autotune %.1f s -> %s r %s z %s" % (time.perf_counter() - t0, tuned["layout"],
+              tuned["r"]["shape"], tuned["z"]["shape"]), file=sys.stderr, flush=True)
     p.set_check(100, 1e-9)
     p.set_graph_steps(args.graph_steps)
     active = int(np.count_nonzero(p.region_map() != 255))
@@ -191,7 +191,8 @@ def main():
                                "%d steps, energy check every 100 steps"
                                % (spec.nr, spec.nz, args.seed, "Peaceman-Rachford", spec.dt, args.steps),
                    "active_cells": active, "cells": cells, "graph_steps": args.graph_steps,
-                   "launch_r": list(p.get_launch(0)), "launch_z": list(p.get_launch(1))},
+                   "layout": p.layout(), "launch_r": list(p.get_launch(0)),
+                   "launch_z": list(p.get_launch(1))},
         "roofline": {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "ms_per_launch": {"sweep_r": ms_r, "sweep_z": ms_z},

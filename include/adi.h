@@ -52,6 +52,14 @@ typedef enum {
  *   in Sec. 3): r implicit over tau with the source, then z implicit over tau. */
 typedef enum { ADI_PR = 0, ADI_LOD_BE = 1 } adi_scheme;
 
+/* Storage of the right-hand sides carried between sweeps (the field T is
+ * always stored by rows, r fastest):
+ *   ADI_LAYOUT_ROWS    by rows, like T; any grid size;
+ *   ADI_LAYOUT_STRIPS  strips of 4 columns, each strip a contiguous run of
+ *                      rows of 4 values, so that both sweeps move whole
+ *                      cache lines; nr <= 2048 and nz <= 3072. */
+typedef enum { ADI_LAYOUT_ROWS = 0, ADI_LAYOUT_STRIPS = 1 } adi_layout;
+
 /* Geometry of Fig. 1 (Sec. 2): cooler r < r0 for z < zmax; inner insulator
  * r0 <= r < r1, heater r1 <= r < r2, outer insulator r2 <= r < rmax, all three
  * for z < z0; terminal slab zmax <= z < ztop over the whole radius; cells with
@@ -158,16 +166,29 @@ adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_
  * waves_per_line waves; each lane handles lines_per_lane lines; a workgroup
  * runs groups_per_block line groups.  (64/lines_per_wave)*waves_per_line*chunk
  * must cover the line length.  Only compiled shapes are accepted
- * (ADI_EUNSUPPORTED otherwise); see adi_launch_shapes. */
+ * (ADI_EUNSUPPORTED otherwise); see adi_layout_shapes: the shape must
+ * belong to the problem's layout. */
 adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lines_per_wave,
                           int32_t waves_per_line, int32_t lines_per_lane, int32_t groups_per_block);
 adi_status adi_get_launch(adi_problem p, int32_t dir, int32_t* chunk, int32_t* lines_per_wave,
                           int32_t* waves_per_line, int32_t* lines_per_lane, int32_t* groups_per_block);
 
-/* Launch shapes compiled into this build: writes up to max_shapes records
- * (chunk, lines_per_wave, waves_per_line, lines_per_lane, groups_per_block)
- * to out (5*max_shapes int32) and the number of shapes to *count. */
+/* Launch shapes compiled into this build for the rows layout: writes up to
+ * max_shapes records (chunk, lines_per_wave, waves_per_line, lines_per_lane,
+ * groups_per_block) to out (5*max_shapes int32) and the number of shapes to
+ * *count. */
 adi_status adi_launch_shapes(int32_t* out, int32_t max_shapes, int32_t* count);
+
+/* Same for a layout and direction (dir 0 = r, 1 = z).  Strip-layout shapes
+ * are (chunk, 1, waves, 4, 1): one line slot per wave, 4 lines per lane. */
+adi_status adi_layout_shapes(int32_t layout, int32_t dir, int32_t* out, int32_t max_shapes, int32_t* count);
+
+/* Choose the right-hand-side layout (adi_layout); resets both launch shapes
+ * to the layout's defaults.  Results do not depend on the layout beyond
+ * rounding order (the same tables and arithmetic per line).  Synchronises.
+ * ADI_EUNSUPPORTED if the grid exceeds the layout's kernels. */
+adi_status adi_set_layout(adi_problem p, int32_t layout);
+adi_status adi_get_layout(adi_problem p, int32_t* layout);
 
 /* Steps per captured HIP graph in adi_step (0 = plain launches). */
 adi_status adi_set_graph_steps(adi_problem p, int32_t steps);

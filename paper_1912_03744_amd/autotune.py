@@ -1,10 +1,11 @@
 """Launch-shape autotuner for the line-solve sweeps and the ragged batch.
 
-Single problems: for each sweep direction it times every compiled launch
-shape (cells per chunk, lines per wave, waves per line, lines per lane,
-groups per workgroup) that covers the line length without too much padding,
-using adi_time_sweeps (HIP events on the problem's stream), and keeps the
-fastest.  Ragged batches: it times the persistent batch kernel (lines per
+Single problems: for each right-hand-side layout (rows, strips of 4
+columns) and sweep direction it times every compiled launch shape (cells per
+chunk, lines per wave, waves per line, lines per lane, groups per workgroup)
+that covers the line length without too much padding, using
+adi_time_sweeps (HIP events on the problem's stream), and keeps the layout
+and shapes with the smallest time per step.  Ragged batches: it times the persistent batch kernel (lines per
 lane, waves per workgroup, resident workgroups per compute unit) on a short
 run of the batch itself with adi_batch_time.  Results are cached in a JSON
 file keyed by GPU architecture, problem size (or the batch's size mix) and
@@ -55,54 +56,81 @@ def key(nr, nz, scheme):
     return "%s/%dx%d/%s" % (_arch(), nr, nz, scheme)
 
 
-def candidates(n, nlines, max_pad=2.0):
+def candidates(n, nlines, max_pad=2.0, layout="rows", direction=0):
     """Compiled shapes (chunk, lines_per_wave, waves_per_line, lines_per_lane,
-    groups_per_block) covering a line of n cells with at most max_pad
-    padding."""
+    groups_per_block) of a layout covering a line of n cells with at most
+    max_pad padding."""
     out = []
-    for m, lpw, wpl, r, ngw in native.launch_shapes():
+    shapes = native.launch_shapes() if layout == "rows" else native.layout_shapes(layout, direction)
+    for m, lpw, wpl, r, ngw in shapes:
         G = (64 // lpw) * wpl
         if G * m < n or G * m > max_pad * max(n, 16):
             continue
-        if lpw * r > max(1, nlines):
+        if layout == "rows" and lpw * r > max(1, nlines):
             continue
         out.append((m, lpw, wpl, r, ngw))
     return out
 
 
-def tune(problem, dt, nlaunch=20, reps=2, verbose=False, log=None):
-    """Time every candidate shape in both directions and set the fastest.
-    Returns {"r": (shape, ms), "z": (shape, ms), "trials": [...]}."""
+def _tune_layout(problem, dt, layout, nlaunch, reps, verbose, log):
     res = {"trials": []}
     dims = {0: (problem.nr, problem.nz), 1: (problem.nz, problem.nr)}
     for d in (0, 1):
         n, nlines = dims[d]
         best = None
-        for shape in candidates(n, nlines):
+        for shape in candidates(n, nlines, layout=layout, direction=d):
             problem.set_launch(d, *shape)
             t = min(problem.time_sweeps(dt, nlaunch)[d] for _ in range(reps))
-            res["trials"].append({"dir": d, "shape": shape, "ms": t})
+            res["trials"].append({"layout": layout, "dir": d, "shape": shape, "ms": t})
             if verbose:
-                msg = "autotune dir %d shape %s: %.4f ms" % (d, shape, t)
+                msg = "autotune %s dir %d shape %s: %.4f ms" % (layout, d, shape, t)
                 print(msg, flush=True) if log is None else log(msg)
             if best is None or t < best[1]:
                 best = (shape, t)
+        if best is None:
+            return None
         problem.set_launch(d, *best[0])
         res["rz"[d]] = best
     return res
 
 
+def tune(problem, dt, nlaunch=20, reps=2, verbose=False, log=None):
+    """Time every candidate shape of every layout in both directions and set
+    the layout and shapes with the smallest r + z time.  Returns {"layout":
+    name, "r": (shape, ms), "z": (shape, ms), "trials": [...]}."""
+    best, trials = None, []
+    for layout in native.LAYOUTS:
+        try:
+            problem.set_layout(layout)
+        except native.AdiError:
+            continue
+        res = _tune_layout(problem, dt, layout, nlaunch, reps, verbose, log)
+        if res is None:
+            continue
+        trials += res["trials"]
+        total = res["r"][1] + res["z"][1]
+        if best is None or total < best[0]:
+            best = (total, layout, res)
+    _, layout, res = best
+    problem.set_layout(layout)
+    for d in (0, 1):
+        problem.set_launch(d, *res["rz"[d]][0])
+    return {"layout": layout, "r": res["r"], "z": res["z"], "trials": trials}
+
+
 def apply(problem, dt, scheme, retune=False, verbose=False, log=None):
-    """Set the cached best shapes for this problem size, tuning on a miss."""
+    """Set the cached best layout and shapes for this problem size, tuning on
+    a miss."""
     db = _load()
     k = key(problem.nr, problem.nz, scheme)
-    if not retune and k in db:
+    if not retune and k in db and "layout" in db[k]:
+        problem.set_layout(db[k]["layout"])
         for d, name in ((0, "r"), (1, "z")):
             problem.set_launch(d, *db[k][name]["shape"])
         return db[k]
     t0 = time.time()
     r = tune(problem, dt, verbose=verbose, log=log)
-    entry = {"r": {"shape": list(r["r"][0]), "ms": r["r"][1]},
+    entry = {"layout": r["layout"], "r": {"shape": list(r["r"][0]), "ms": r["r"][1]},
              "z": {"shape": list(r["z"][0]), "ms": r["z"][1]},
              "seconds": time.time() - t0, "trials": len(r["trials"])}
     db = _load()

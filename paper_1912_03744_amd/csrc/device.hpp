@@ -671,4 +671,209 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
   }
 }
 
+// ------------------------------------------------------ lane-block solver --
+
+// Loads through a pointer the compiler knows to be global memory.
+typedef const __attribute__((address_space(1))) double* gptr;
+
+// The factor-table values one lane needs for its chunk k of a line class:
+// interior factors (rows 1..M-2), output operator (all rows), reduced-system
+// factors of the chunk.  Loaded once, ahead of the data.
+template <int M>
+struct LaneTab {
+  double w[M], qa[M], cp[M], sp[M], sr[M];
+  double od[M], ol[M], ou[M], oc[M];
+  double cs, ae, W0, Q0, C0, W1, Q1, C1, cprev;
+};
+
+// pos/chk: class tables already offset by the lane's chunk k; G chunks.
+template <int M, int G>
+__device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, const double* chk_) {
+  constexpr int GM = G * M;
+  const gptr pos = (gptr)pos_;
+  const gptr chk = (gptr)chk_;
+#pragma unroll
+  for (int t = 1; t <= M - 2; ++t) {
+    L.w[t] = pos[P_W * GM + t * G];
+    L.qa[t] = pos[P_QA * GM + t * G];
+    L.cp[t] = pos[P_CP * GM + t * G];
+    L.sp[t] = pos[P_SP * GM + t * G];
+    L.sr[t] = pos[P_SR * GM + t * G];
+  }
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    L.od[t] = pos[P_OD * GM + t * G];
+    L.ol[t] = pos[P_OL * GM + t * G];
+    L.ou[t] = pos[P_OU * GM + t * G];
+    L.oc[t] = pos[P_OC * GM + t * G];
+  }
+  L.cs = chk[C_CS * G]; L.ae = chk[C_AE * G];
+  L.W0 = chk[C_W0 * G]; L.Q0 = chk[C_Q0 * G]; L.C0 = chk[C_C0 * G];
+  L.W1 = chk[C_W1 * G]; L.Q1 = chk[C_Q1 * G]; L.C1 = chk[C_C1 * G];
+  L.cprev = chk[C_CPREV * G];
+}
+
+// Solve a block of R lines that share one line class.  Lane k = 64*wave +
+// lane holds chunk k (M cells) of each of the R lines in v[R][M]; the NW
+// waves of the workgroup hold the G = 64*NW chunks of the lines.  Same
+// partition method as solve_group (interior elimination with the class's
+// precomputed factors, reduced system by recursive doubling over the chunks,
+// back substitution), with data and factors already in registers.  On
+// return v holds the solution and o the next half step's right-hand side
+// without the crossing constants, 0 outside the domain.  `lds` holds
+// NW*(R+1) doubles.  Every lane of the workgroup must call this (it contains
+// barriers when NW > 1).
+template <int M, int NW, int R>
+__device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], const LaneTab<M>& L,
+                                            unsigned long long live, double* lds) {
+  static_assert(M >= 3, "chunks need an interior row");
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+      if (!((live >> t) & 1ull)) v[r][t] = 0.0;
+
+  // interior forward elimination and back substitution (rows 1..M-2)
+  double run[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) run[r] = 0.0;
+#pragma unroll
+  for (int t = 1; t <= M - 2; ++t)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      run[r] = v[r][t] * L.w[t] - L.qa[t] * run[r];
+      v[r][t] = run[r];
+    }
+#pragma unroll
+  for (int r = 0; r < R; ++r) run[r] = 0.0;
+#pragma unroll
+  for (int t = M - 2; t >= 1; --t)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      run[r] = v[r][t] - L.cp[t] * run[r];
+      v[r][t] = run[r];
+    }
+
+  // reduced system, forward recurrence over the chunks
+  double g0w[R], F[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    g0w[r] = (v[r][0] - L.cs * v[r][1]) * L.W0;
+    F[r] = (v[r][M - 1] - L.ae * v[r][M - 2]) * L.W1 - L.Q1 * g0w[r];
+  }
+  double B = L.Q1 * L.Q0;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double Bo = __shfl_up(B, d, 64);
+    double Ao[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Ao[r] = __shfl_up(F[r], d, 64);
+    if (lane >= d) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) F[r] += B * Ao[r];
+      B *= Bo;
+    }
+  }
+  double Fin[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) Fin[r] = 0.0;
+  if constexpr (NW > 1) {
+    double* slot = lds + wv * (R + 1);
+    if (lane == 63) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) slot[r] = F[r];
+      slot[R] = B;
+    }
+    __syncthreads();
+    for (int w = 0; w < wv; ++w) {
+      const double* q = lds + w * (R + 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) Fin[r] = q[r] + q[R] * Fin[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] += B * Fin[r];
+    __syncthreads();
+  }
+  double Fprev[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    Fprev[r] = __shfl_up(F[r], 1, 64);
+    if (lane == 0) Fprev[r] = Fin[r];
+  }
+
+  // backward recurrence
+  double U[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) U[r] = g0w[r] - L.Q0 * Fprev[r] - L.C0 * F[r];
+  double E = L.C0 * L.C1;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double Eo = __shfl_down(E, d, 64);
+    double Uo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Uo[r] = __shfl_down(U[r], d, 64);
+    if (lane + d < 64) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) U[r] += E * Uo[r];
+      E *= Eo;
+    }
+  }
+  double Uin[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) Uin[r] = 0.0;
+  if constexpr (NW > 1) {
+    double* slot = lds + wv * (R + 1);
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) slot[r] = U[r];
+      slot[R] = E;
+    }
+    __syncthreads();
+    for (int w = NW - 1; w > wv; --w) {
+      const double* q = lds + w * (R + 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) Uin[r] = q[r] + q[R] * Uin[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) U[r] += E * Uin[r];
+    __syncthreads();
+  }
+
+  // chunk ends, their outer neighbours, interior back substitution
+  double xm1[R], xp1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double un = __shfl_down(U[r], 1, 64);
+    if (lane == 63) un = Uin[r];
+    const double xs = U[r];
+    const double xe = F[r] - L.C1 * un;
+    xm1[r] = Fprev[r] - L.cprev * U[r];
+    xp1[r] = un;
+    v[r][0] = xs;
+    v[r][M - 1] = xe;
+    F[r] = xs;
+    U[r] = xe;
+  }
+#pragma unroll
+  for (int t = 1; t <= M - 2; ++t)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r][t] = v[r][t] - L.sp[t] * F[r] - L.sr[t] * U[r];
+
+  // next half step's right-hand side
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const bool lv = (live >> t) & 1ull;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double xl = t > 0 ? v[r][t > 0 ? t - 1 : 0] : xm1[r];
+      const double xr = t < M - 1 ? v[r][t < M - 1 ? t + 1 : t] : xp1[r];
+      const double y = L.od[t] * v[r][t] + L.ol[t] * xl + L.ou[t] * xr + L.oc[t];
+      o[r][t] = lv ? y : 0.0;
+    }
+  }
+}
+
 }  // namespace adi

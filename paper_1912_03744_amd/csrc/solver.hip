@@ -17,6 +17,7 @@
 
 #include "common.hpp"
 #include "device.hpp"
+#include "strip.hpp"
 
 namespace adi {
 
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(256) k_assemble(Params P, Geom g, DirTabs r, D
 // Right-hand side of the first r half step from a field T: the z-direction
 // output operator applied to T plus the r boundary constant.
 __global__ void k_init_rhs(const double* __restrict__ T, double* __restrict__ d, Geom g,
-                           DirTabs z, const double* __restrict__ rxc, int nr, int nz) {
+                           DirTabs z, const double* __restrict__ rxc, int nr, int nz, long strip) {
   const long n = (long)nr * nz;
   for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n; c += (long)gridDim.x * blockDim.x) {
     const int i = (int)(c % nr), j = (int)(c / nr);
@@ -116,19 +117,8 @@ __global__ void k_init_rhs(const double* __restrict__ T, double* __restrict__ d,
     double o = pos[P_OD * GM + ix] * T[c] + pos[P_OC * GM + ix] + rxc[(long)bet * nr + i];
     if (j > 0) o += pos[P_OL * GM + ix] * T[c - nr];
     if (j < nz - 1) o += pos[P_OU * GM + ix] * T[c + nr];
-    d[c] = o;
+    d[strip ? (long)(i >> 2) * strip + 4L * j + (i & 3) : c] = o;
   }
-}
-
-// Workgroups are dealt to the 8 XCDs round-robin by block index; remap so
-// that each XCD gets one contiguous range of line groups, which keeps
-// neighbouring lines (sharing cache lines in the strided direction) in one
-// L2.  A bijection on [0, nblocks).
-__device__ __forceinline__ int xcd_block(int b, int nblocks) {
-  constexpr int NX = 8;
-  const int q = nblocks / NX, rem = nblocks % NX;
-  const int x = b % NX, slot = b / NX;
-  return x * q + (x < rem ? x : rem) + slot;
 }
 
 // NGW line groups per workgroup, WPL waves per group.  The grid has one
@@ -305,6 +295,31 @@ static int find_variant(int M, int LPW, int WPL, int R, int NGW) {
   return -1;
 }
 
+// Strip-layout kernels: r sweeps take 4 cells per chunk and NW waves (lines
+// up to 256*NW cells); z sweeps take M cells per chunk and NW waves (lines up
+// to 64*NW*M cells, LDS 8*64*NW*(4M+2) bytes).
+using StripFn = void (*)(StripArgs);
+struct StripVariant {
+  int dir, M, NW;
+  StripFn fn;
+};
+#define ADI_SR(nw) {0, 4, nw, k_sweep_rs<nw>}
+#define ADI_SZ(m, nw) {1, m, nw, k_sweep_zs<m, nw>}
+static const StripVariant kStrip[] = {
+    ADI_SR(1), ADI_SR(2), ADI_SR(4), ADI_SR(8),
+    ADI_SZ(3, 1), ADI_SZ(5, 1), ADI_SZ(8, 1), ADI_SZ(5, 2), ADI_SZ(8, 2), ADI_SZ(5, 4), ADI_SZ(10, 4),
+    ADI_SZ(4, 8), ADI_SZ(5, 8), ADI_SZ(3, 16),
+};
+#undef ADI_SR
+#undef ADI_SZ
+static const int kNumStrip = sizeof(kStrip) / sizeof(kStrip[0]);
+
+static int find_strip(int dir, int M, int NW) {
+  for (int v = 0; v < kNumStrip; ++v)
+    if (kStrip[v].dir == dir && kStrip[v].M == M && kStrip[v].NW == NW) return v;
+  return -1;
+}
+
 }  // namespace adi
 
 using namespace adi;
@@ -316,12 +331,14 @@ namespace {
 struct Launch {
   int M = 0, LPW = 0, WPL = 0, R = 1, NGW = 1;  // shape
   int G = 0, variant = -1;
+  int layout = ADI_LAYOUT_ROWS;  // kernel family; variant indexes kVariants or kStrip
 };
 
 struct DirState {
   Launch L;
   int n = 0, nlines = 0, ncls = 0;
   LineTab* tabs = nullptr;
+  LineTab htabs[MAX_CLS] = {};  // host copy (the strip kernels take them by value)
   double *pos = nullptr, *chk = nullptr, *eng = nullptr, *xc = nullptr, *work = nullptr;
   DirTabs view() const {
     DirTabs d;
@@ -330,6 +347,39 @@ struct DirState {
     return d;
   }
 };
+
+adi_status validate_strip_launch(int dir, int n, int chunk, int lpw, int wpl, int r, int ngw, Launch* out) {
+  const int v = lpw == 1 && r == 4 && ngw == 1 ? find_strip(dir, chunk, wpl) : -1;
+  if (v < 0)
+    return fail(ADI_EUNSUPPORTED, "no strip-layout %s kernel for chunk %d, %d lines/wave, %d waves, %d lines/lane, "
+                "%d groups/block", dir == 0 ? "r" : "z", chunk, lpw, wpl, r, ngw);
+  const int G = 64 * wpl;
+  if ((long)G * chunk < n)
+    return fail(ADI_EINVAL, "%d chunks of %d cells do not cover a line of %d", G, chunk, n);
+  out->M = chunk; out->LPW = 1; out->WPL = wpl; out->R = 4; out->NGW = 1;
+  out->G = G; out->variant = v; out->layout = ADI_LAYOUT_STRIPS;
+  return ADI_OK;
+}
+
+// Strip-layout default: least padding, then the most waves up to 8.
+bool default_strip_launch(int dir, int n, Launch* out) {
+  int best = -1;
+  double best_score = -1e300;
+  for (int v = 0; v < kNumStrip; ++v) {
+    const StripVariant& V = kStrip[v];
+    if (V.dir != dir) continue;
+    const long cover = 64L * V.NW * V.M;
+    if (cover < n) continue;
+    const double score = -8.0 * std::log2((double)cover / n) - std::fabs(std::log2(V.NW / 8.0));
+    if (score > best_score) best_score = score, best = v;
+  }
+  if (best < 0) return false;
+  Launch L;
+  L.M = kStrip[best].M; L.LPW = 1; L.WPL = kStrip[best].NW; L.R = 4; L.NGW = 1;
+  L.G = 64 * L.WPL; L.variant = best; L.layout = ADI_LAYOUT_STRIPS;
+  *out = L;
+  return true;
+}
 
 adi_status validate_launch(int n, int chunk, int lpw, int wpl, int r, int ngw, Launch* out) {
   const int v = find_variant(chunk, lpw, wpl, r, ngw);
@@ -390,6 +440,8 @@ struct adi_problem_s {
   double tabs_dt = 0.0;
   bool rhs_valid = false;
   double *T = nullptr, *dA = nullptr, *dB = nullptr, *mid = nullptr;
+  int layout = ADI_LAYOUT_ROWS;  // layout of dA / dB (and of mid when a z sweep writes it)
+  long strip = 0;                // doubles per strip in the strip layout
   double *part = nullptr, *eout = nullptr, *state = nullptr, *prof = nullptr;
   uint8_t* dmap = nullptr;
   int* dranges = nullptr;
@@ -478,6 +530,9 @@ adi_status ensure_tables(adi_problem p, double dt) {
   hipLaunchKernelGGL(k_assemble, dim3(p->r.ncls + p->z.ncls), dim3(256), 0, p->stream, p->P, p->g,
                      p->r.view(), p->z.view());
   ADI_CHECK_LAUNCH();
+  for (DirState* D : {&p->r, &p->z})
+    ADI_HIP(hipMemcpyAsync(D->htabs, D->tabs, sizeof(LineTab) * D->ncls, hipMemcpyDeviceToHost, p->stream));
+  ADI_HIP(hipStreamSynchronize(p->stream));
   p->tabs_valid = true;
   p->tabs_dt = dt;
   p->rhs_valid = false;
@@ -489,14 +544,66 @@ adi_status launch_init_rhs(adi_problem p) {
   const long n = (long)p->P.nr * p->P.nz;
   const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_init_rhs, dim3(blocks), dim3(256), 0, p->stream, p->T, p->dA, p->g, p->z.view(),
-                     p->r.xc, p->P.nr, p->P.nz);
+                     p->r.xc, p->P.nr, p->P.nz, p->layout == ADI_LAYOUT_STRIPS ? p->strip : 0L);
   ADI_CHECK_LAUNCH();
   p->rhs_valid = true;
   return ADI_OK;
 }
 
+// Cumulative class ends along one axis (dir 0: rows by band, 1: columns by
+// class): the class of index x is the number of q with x >= ends[q].
+void class_ends(const int* ranges, int dir, int ncls, int* ends) {
+  int e = 0;
+  for (int c = 0; c < 3; ++c) {
+    if (c < ncls) {
+      const int* rg = ranges + (dir * MAX_CLS + c) * 2;
+      if (rg[1] > rg[0]) e = rg[1];
+      ends[c] = c < ncls - 1 ? e : INT32_MAX;
+    } else {
+      ends[c] = INT32_MAX;
+    }
+  }
+}
+
+adi_status launch_strip_sweep(adi_problem p, int dir, const double* din, double* dout, double* xout) {
+  const DirState& D = dir == 0 ? p->r : p->z;
+  const DirState& X = dir == 0 ? p->z : p->r;
+  StripArgs a;
+  a.din = din;
+  a.dout = dout;
+  a.xout = xout;
+  for (int c = 0; c < MAX_CLS; ++c) a.tabs[c] = D.htabs[c < D.ncls ? c : 0];
+  bool ambient = false;
+  for (int c = 0; c < 4; ++c) ambient = ambient || p->P.tinf[c] != 0.0;
+  a.xc = ambient ? X.xc : nullptr;  // the crossing constants vanish with zero ambient temperatures
+  a.strip = p->strip;
+  a.nr = p->P.nr;
+  a.nz = p->P.nz;
+  a.nlines = D.nlines;
+  a.nblocks = (D.nlines + 3) / 4;
+  // lines of this direction: rows (bands) for r, columns (classes) for z
+  class_ends(p->ranges, dir == 0 ? 0 : 1, D.ncls, a.line_end);
+  class_ends(p->ranges, dir == 0 ? 1 : 0, X.ncls, a.pos_end);
+  a.nxcls = X.ncls;
+  a.nmix = 0;
+  for (int q = 0; q < 3; ++q) {
+    const int e = a.line_end[q];
+    if (e <= 0 || e >= D.nlines || e % 4 == 0) continue;
+    const int blk = e / 4;
+    bool seen = false;
+    for (int m = 0; m < a.nmix; ++m) seen = seen || a.mix[m] == blk;
+    if (!seen) a.mix[a.nmix++] = blk;
+  }
+  for (int m = a.nmix; m < 4; ++m) a.mix[m] = -1;
+  const StripVariant& V = kStrip[D.L.variant];
+  hipLaunchKernelGGL(V.fn, dim3(a.nblocks + 4 * a.nmix), dim3(64 * V.NW), 0, p->stream, a);
+  ADI_CHECK_LAUNCH();
+  return ADI_OK;
+}
+
 adi_status launch_sweep(adi_problem p, int dir, const double* din, double* dout, double* xout) {
   const DirState& D = dir == 0 ? p->r : p->z;
+  if (D.L.layout == ADI_LAYOUT_STRIPS) return launch_strip_sweep(p, dir, din, dout, xout);
   SweepArgs a;
   a.din = din;
   a.dout = dout;
@@ -730,9 +837,14 @@ adi_status adi_create_problem(const adi_geometry* g, const adi_bc* bc, adi_schem
   p->g.kap = (uint8_t*)gd;
   p->g.bet = p->g.kap + nr;
   // field and work buffers
+  // dA, dB and mid also hold the strip layout: ceil(nr/4) strips, each of
+  // 4*ceil(nz/4) rows of 4 doubles
+  p->strip = 4L * (4L * ((nz + 3) / 4));
+  const long nbuf = std::max(n, (long)((nr + 3) / 4) * p->strip);
   double** bufs[] = {&p->T, &p->dA, &p->dB, &p->mid};
   for (double** b : bufs)
-    if ((st = dev_alloc((void**)b, sizeof(double) * n, p->stream)) != ADI_OK) return cleanup(st);
+    if ((st = dev_alloc((void**)b, sizeof(double) * (b == &p->T ? n : nbuf), p->stream)) != ADI_OK)
+      return cleanup(st);
   if ((st = dev_alloc((void**)&p->part, sizeof(double) * 4 * nz, p->stream)) != ADI_OK) return cleanup(st);
   if ((st = dev_alloc((void**)&p->eout, sizeof(double) * 16, p->stream)) != ADI_OK) return cleanup(st);
   if ((st = dev_alloc((void**)&p->state, sizeof(double) * 8, p->stream)) != ADI_OK) return cleanup(st);
@@ -977,7 +1089,11 @@ adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lin
   if (dir != 0 && dir != 1) return fail(ADI_EINVAL, "dir must be 0 (r) or 1 (z)");
   DirState& D = dir == 0 ? p->r : p->z;
   Launch L;
-  ADI_TRY(validate_launch(D.n, chunk, lines_per_wave, waves_per_line, lines_per_lane, groups_per_block, &L));
+  if (p->layout == ADI_LAYOUT_STRIPS)
+    ADI_TRY(validate_strip_launch(dir, D.n, chunk, lines_per_wave, waves_per_line, lines_per_lane,
+                                  groups_per_block, &L));
+  else
+    ADI_TRY(validate_launch(D.n, chunk, lines_per_wave, waves_per_line, lines_per_lane, groups_per_block, &L));
   const bool shape_change = L.G != D.L.G || L.M != D.L.M;
   D.L = L;
   if (shape_change) {
@@ -989,6 +1105,59 @@ adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lin
     p->tabs_valid = false;
   }
   drop_graphs(p);
+  return ADI_OK;
+}
+
+adi_status adi_set_layout(adi_problem p, int32_t layout) {
+  ADI_TRY(check_handle(p));
+  if (layout != ADI_LAYOUT_ROWS && layout != ADI_LAYOUT_STRIPS)
+    return fail(ADI_EINVAL, "unknown layout %d", (int)layout);
+  if (layout == p->layout) return ADI_OK;
+  Launch Lr, Lz;
+  if (layout == ADI_LAYOUT_STRIPS) {
+    if (!default_strip_launch(0, p->P.nr, &Lr) || !default_strip_launch(1, p->P.nz, &Lz))
+      return fail(ADI_EUNSUPPORTED, "grid %dx%d exceeds the strip-layout kernels (nr <= 2048, nz <= 3072)",
+                  p->P.nr, p->P.nz);
+  } else {
+    Lr = default_launch(0, p->P.nr, p->P.nz);
+    Lz = default_launch(1, p->P.nz, p->P.nr);
+  }
+  // the carried right-hand side is re-derived from T in the new layout
+  ADI_HIP(hipStreamSynchronize(p->stream));
+  p->r.L = Lr;
+  p->z.L = Lz;
+  p->layout = layout;
+  dev_free(p->tab_mem);
+  p->tab_mem = nullptr;
+  p->tabs_valid = false;
+  p->rhs_valid = false;
+  drop_graphs(p);
+  return ADI_OK;
+}
+
+adi_status adi_get_layout(adi_problem p, int32_t* layout) {
+  ADI_TRY(check_handle(p));
+  if (!layout) return fail(ADI_EINVAL, "null output");
+  *layout = p->layout;
+  return ADI_OK;
+}
+
+adi_status adi_layout_shapes(int32_t layout, int32_t dir, int32_t* out, int32_t max_shapes, int32_t* count) {
+  if (!count) return fail(ADI_EINVAL, "null count");
+  if (max_shapes > 0 && !out) return fail(ADI_EINVAL, "null output array");
+  if (dir != 0 && dir != 1) return fail(ADI_EINVAL, "dir must be 0 (r) or 1 (z)");
+  if (layout == ADI_LAYOUT_ROWS) return adi_launch_shapes(out, max_shapes, count);
+  if (layout != ADI_LAYOUT_STRIPS) return fail(ADI_EINVAL, "unknown layout %d", (int)layout);
+  int c = 0;
+  for (int v = 0; v < kNumStrip; ++v) {
+    if (kStrip[v].dir != dir) continue;
+    if (c < max_shapes) {
+      const int32_t f[5] = {kStrip[v].M, 1, kStrip[v].NW, 4, 1};
+      for (int q = 0; q < 5; ++q) out[5 * c + q] = f[q];
+    }
+    ++c;
+  }
+  *count = c;
   return ADI_OK;
 }
 

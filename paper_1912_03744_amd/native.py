@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libadi.so")
 ADI_OK, ADI_EINVAL, ADI_ENOMEM, ADI_EDEVICE, ADI_ESTATE = 0, -1, -2, -3, -4
 ADI_ENONFINITE, ADI_EBALANCE, ADI_EUNSUPPORTED = -5, -6, -7
 SCHEMES = {"pr": 0, "lod": 1}
+LAYOUTS = {"rows": 0, "strips": 1}
 
 
 class AdiError(RuntimeError):
@@ -80,6 +81,9 @@ _SIGS = {
     "adi_get_launch": [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p],
     "adi_set_graph_steps": [_vp, ctypes.c_int32],
     "adi_launch_shapes": [_i32p, ctypes.c_int32, _i32p],
+    "adi_layout_shapes": [ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int32, _i32p],
+    "adi_set_layout": [_vp, ctypes.c_int32],
+    "adi_get_layout": [_vp, _i32p],
     "adi_destroy": [_vp],
     "adi_create_batch": [ctypes.c_int32, ctypes.POINTER(Geometry), ctypes.POINTER(BC), ctypes.c_int,
                          _vp, ctypes.POINTER(_vp)],
@@ -259,6 +263,15 @@ class Problem:
         check(lib().adi_get_launch(self._h, int(direction), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
+    def set_layout(self, layout):
+        """"rows" or "strips" (adi_set_layout); resets the launch shapes."""
+        check(lib().adi_set_layout(self._h, LAYOUTS[layout]))
+
+    def layout(self):
+        v = ctypes.c_int32()
+        check(lib().adi_get_layout(self._h, ctypes.byref(v)))
+        return {b: a for a, b in LAYOUTS.items()}[v.value]
+
 
 class Batch:
     """A ragged batch of independent instances (adi_create_batch ...)."""
@@ -425,6 +438,16 @@ def launch_shapes():
     check(lib().adi_launch_shapes(None, 0, ctypes.byref(n)))
     buf = (ctypes.c_int32 * (5 * n.value))()
     check(lib().adi_launch_shapes(buf, n.value, ctypes.byref(n)))
+    return [tuple(buf[5 * i:5 * i + 5]) for i in range(n.value)]
+
+
+def layout_shapes(layout, direction):
+    """Compiled launch shapes of a layout ("rows" or "strips") for one
+    direction (0 = r, 1 = z)."""
+    n = ctypes.c_int32()
+    check(lib().adi_layout_shapes(LAYOUTS[layout], int(direction), None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_int32 * max(1, 5 * n.value))()
+    check(lib().adi_layout_shapes(LAYOUTS[layout], int(direction), buf, n.value, ctypes.byref(n)))
     return [tuple(buf[5 * i:5 * i + 5]) for i in range(n.value)]
 
 

@@ -29,9 +29,11 @@ def run_oracle(spec, nsteps, T0=None):
     return P, out, mid
 
 
-def run_gpu(spec, nsteps, launch=None, T0=None, graph_steps=0, check_every=0, tune=False):
+def run_gpu(spec, nsteps, launch=None, T0=None, graph_steps=0, check_every=0, tune=False, layout=None):
     from paper_1912_03744_amd import native
     p = native.Problem.from_spec(spec)
+    if layout:
+        p.set_layout(layout)
     if tune:
         from paper_1912_03744_amd import autotune
         autotune.apply(p, spec.dt, spec.scheme)

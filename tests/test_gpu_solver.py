@@ -91,6 +91,67 @@ def test_launch_shapes_ragged(shape):
         pytest.skip("shape covers none of the line lengths")
 
 
+def _strip_shapes():
+    from paper_1912_03744_amd import native
+    return [(d, sh) for d in (0, 1) for sh in native.layout_shapes("strips", d)]
+
+
+@pytest.mark.parametrize("dshape", _strip_shapes() if gpu_available() else [],
+                         ids=lambda x: "d%d_m%d_w%d" % (x[0], x[1][0], x[1][2]))
+def test_strip_layout_shapes_ragged(dshape):
+    """Every strip-layout kernel (right-hand sides in strips of 4 columns) on
+    grids with partial strips and partial row groups, strips and row groups
+    straddling class boundaries, both schemes."""
+    d, shape = dshape
+    m, _, nw, _, _ = shape
+    cover = 64 * nw * m
+    ran = 0
+    for nr, nz in ((37, 91), (150, 333), (1030, 2570), (1024, 2560)):
+        n = nr if d == 0 else nz
+        if cover < n or (cover > 4 * n and n > 100):
+            continue
+        s = W.production(3, nr=nr, nz=nz).replace(dt=2e-3)
+        for scheme in (("pr", "lod") if nr < 1000 else ("pr",)):
+            ss = s.replace(scheme=scheme)
+            _say("strip shape %s grid %dx%d dir %d scheme %s" % (shape, nr, nz, d, scheme))
+            steps = 5 if nr < 1000 else 2
+            P, want, _ = run_oracle(ss, steps)
+            p, got = run_gpu(ss, steps, launch={d: shape}, layout="strips")
+            assert p.layout() == "strips"
+            assert rel_inf(got, want, P.active()) <= TOL, (shape, d, scheme)
+            ran += 1
+    if not ran:
+        pytest.skip("shape covers none of the line lengths")
+
+
+@pytest.mark.parametrize("scheme", ["pr", "lod"])
+def test_strip_layout_ambient_films_and_checks(scheme):
+    """Strip layout with non-zero ambient temperatures on every face class
+    (the crossing constants), a Dirichlet class, a non-uniform start field,
+    periodic energy checks and graphs, against the oracle; then a switch back
+    to the rows layout continues from the same state."""
+    from paper_1912_03744_amd import native
+    base = tiny_spec(scheme=scheme, dt=0.02)
+    for nr, nz in ((7, 12), (61, 203)):
+        s = base.replace(nr=nr, nz=nz)
+        P = oracle.Problem.from_spec(s)
+        rng = np.random.default_rng(nr)
+        T0 = np.where(P.active(), rng.uniform(0.0, 1.0, P.shape), 0.0)
+        want, _ = P.step(T0, s.scheme, s.dt, 30)
+        want2, _ = P.step(want, s.scheme, s.dt, 10)
+        _say("strip ambient %s %dx%d" % (scheme, nr, nz))
+        p = native.Problem.from_spec(s)
+        p.set_layout("strips")
+        p.set_field(T0)
+        p.set_graph_steps(10)
+        p.set_check(10)
+        p.step(s.dt, 30)
+        assert rel_inf(p.read_field(), want, P.active()) <= TOL
+        p.set_layout("rows")
+        p.step(s.dt, 10)
+        assert rel_inf(p.read_field(), want2, P.active()) <= TOL
+
+
 def test_production_full_size_short_run(tmp_path, monkeypatch):
     """1024 x 2560 at the production time step, in the launch shapes the
     autotuner picks for the benchmark (and in the default shapes): full-field
@@ -100,9 +161,9 @@ def test_production_full_size_short_run(tmp_path, monkeypatch):
     for scheme in ("pr", "lod"):
         s = W.production(0, scheme=scheme)
         P, want, _ = run_oracle(s, 4)
-        for tune in (False, True):
-            _say("production full size %s tuned=%s" % (scheme, tune))
-            p, got = run_gpu(s, 4, tune=tune)
+        for tune, layout in ((False, None), (False, "strips"), (True, None)):
+            _say("production full size %s tuned=%s layout=%s" % (scheme, tune, layout))
+            p, got = run_gpu(s, 4, tune=tune, layout=layout)
             assert rel_inf(got, want, P.active()) <= TOL
 
 
