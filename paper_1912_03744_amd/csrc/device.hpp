@@ -713,6 +713,99 @@ __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, 
   L.cprev = chk[C_CPREV * G];
 }
 
+// ---- wavefront scans of affine maps (x_k = A_k + B_k x_{k-1}) with DPP ----
+//
+// Within each row of 16 lanes the scan takes 4 steps of DPP row shifts
+// (each lane combines with the lane d below or above it; lanes without a
+// source combine with the identity map); the 4 row totals are then read
+// into scalar registers and composed, and each row applies the composition
+// of the rows before (forward) or after (backward) it.
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double old, double src) {
+  const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive forward scan over the 64 lanes: on return lane k holds the
+// composition of the maps of lanes 0..k (F values per line, common factor B).
+template <int R>
+__device__ __forceinline__ void wave_scan_fwd(double (&F)[R], double& B) {
+  const int lane = threadIdx.x & 63;
+#define ADI_FWD_STEP(D)                                              \
+  {                                                                  \
+    const double Bo = dpp_row<0x110 + D>(1.0, B);                    \
+    _Pragma("unroll") for (int r = 0; r < R; ++r) F[r] += B * dpp_row<0x110 + D>(0.0, F[r]); \
+    B *= Bo;                                                         \
+  }
+  ADI_FWD_STEP(1) ADI_FWD_STEP(2) ADI_FWD_STEP(4) ADI_FWD_STEP(8)
+#undef ADI_FWD_STEP
+  // row totals at lanes 15, 31, 47; prefix of the rows below each row
+  const int row = lane >> 4;
+  double cF[R], cB = 1.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) cF[r] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double tB = read_lane(B, 16 * q + 15);
+    double tF[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tF[r] = read_lane(F[r], 16 * q + 15);
+    if (row > q) {  // compose: row total q after the prefix so far
+#pragma unroll
+      for (int r = 0; r < R; ++r) cF[r] = tF[r] + tB * cF[r];
+      cB *= tB;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) F[r] += B * cF[r];
+  B *= cB;
+}
+
+// Inclusive backward scan (x_k = H_k + E_k x_{k+1}): lane k ends with the
+// composition of the maps of lanes k..63.
+template <int R>
+__device__ __forceinline__ void wave_scan_bwd(double (&U)[R], double& E) {
+  const int lane = threadIdx.x & 63;
+#define ADI_BWD_STEP(D)                                              \
+  {                                                                  \
+    const double Eo = dpp_row<0x100 + D>(1.0, E);                    \
+    _Pragma("unroll") for (int r = 0; r < R; ++r) U[r] += E * dpp_row<0x100 + D>(0.0, U[r]); \
+    E *= Eo;                                                         \
+  }
+  ADI_BWD_STEP(1) ADI_BWD_STEP(2) ADI_BWD_STEP(4) ADI_BWD_STEP(8)
+#undef ADI_BWD_STEP
+  // row totals at lanes 48, 32, 16; suffix of the rows above each row
+  const int row = lane >> 4;
+  double cU[R], cE = 1.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) cU[r] = 0.0;
+#pragma unroll
+  for (int q = 3; q >= 1; --q) {
+    const double tE = read_lane(E, 16 * q);
+    double tU[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tU[r] = read_lane(U[r], 16 * q);
+    if (row < q) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) cU[r] = tU[r] + tE * cU[r];
+      cE *= tE;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) U[r] += E * cU[r];
+  E *= cE;
+}
+
 // Solve a block of R lines that share one line class.  Lane k = 64*wave +
 // lane holds chunk k (M cells) of each of the R lines in v[R][M]; the NW
 // waves of the workgroup hold the G = 64*NW chunks of the lines.  Same
@@ -721,8 +814,8 @@ __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, 
 // back substitution), with data and factors already in registers.  On
 // return v holds the solution and o the next half step's right-hand side
 // without the crossing constants, 0 outside the domain.  `lds` holds
-// NW*(R+1) doubles.  Every lane of the workgroup must call this (it contains
-// barriers when NW > 1).
+// 2*NW*(R+1) doubles.  Every lane of the workgroup must call this (it
+// contains barriers when NW > 1).
 template <int M, int NW, int R>
 __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], const LaneTab<M>& L,
                                             unsigned long long live, double* lds) {
@@ -765,37 +858,25 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
     F[r] = (v[r][M - 1] - L.ae * v[r][M - 2]) * L.W1 - L.Q1 * g0w[r];
   }
   double B = L.Q1 * L.Q0;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double Bo = __shfl_up(B, d, 64);
-    double Ao[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) Ao[r] = __shfl_up(F[r], d, 64);
-    if (lane >= d) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) F[r] += B * Ao[r];
-      B *= Bo;
-    }
-  }
+  wave_scan_fwd<R>(F, B);
   double Fin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Fin[r] = 0.0;
   if constexpr (NW > 1) {
-    double* slot = lds + wv * (R + 1);
+    double* slots = lds;  // forward totals of the waves
     if (lane == 63) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) slot[r] = F[r];
-      slot[R] = B;
+      for (int r = 0; r < R; ++r) slots[wv * (R + 1) + r] = F[r];
+      slots[wv * (R + 1) + R] = B;
     }
     __syncthreads();
     for (int w = 0; w < wv; ++w) {
-      const double* q = lds + w * (R + 1);
+      const double* q = slots + w * (R + 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) Fin[r] = q[r] + q[R] * Fin[r];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) F[r] += B * Fin[r];
-    __syncthreads();
   }
   double Fprev[R];
 #pragma unroll
@@ -809,37 +890,25 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
 #pragma unroll
   for (int r = 0; r < R; ++r) U[r] = g0w[r] - L.Q0 * Fprev[r] - L.C0 * F[r];
   double E = L.C0 * L.C1;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double Eo = __shfl_down(E, d, 64);
-    double Uo[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) Uo[r] = __shfl_down(U[r], d, 64);
-    if (lane + d < 64) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) U[r] += E * Uo[r];
-      E *= Eo;
-    }
-  }
+  wave_scan_bwd<R>(U, E);
   double Uin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Uin[r] = 0.0;
   if constexpr (NW > 1) {
-    double* slot = lds + wv * (R + 1);
+    double* slots = lds + NW * (R + 1);  // backward totals (separate: no barrier between phases)
     if (lane == 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) slot[r] = U[r];
-      slot[R] = E;
+      for (int r = 0; r < R; ++r) slots[wv * (R + 1) + r] = U[r];
+      slots[wv * (R + 1) + R] = E;
     }
     __syncthreads();
     for (int w = NW - 1; w > wv; --w) {
-      const double* q = lds + w * (R + 1);
+      const double* q = slots + w * (R + 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) Uin[r] = q[r] + q[R] * Uin[r];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) U[r] += E * Uin[r];
-    __syncthreads();
   }
 
   // chunk ends, their outer neighbours, interior back substitution

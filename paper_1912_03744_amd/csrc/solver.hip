@@ -580,19 +580,21 @@ adi_status launch_strip_sweep(adi_problem p, int dir, const double* din, double*
   a.nr = p->P.nr;
   a.nz = p->P.nz;
   a.nlines = D.nlines;
-  a.nblocks = (D.nlines + 3) / 4;
   // lines of this direction: rows (bands) for r, columns (classes) for z
   class_ends(p->ranges, dir == 0 ? 0 : 1, D.ncls, a.line_end);
   class_ends(p->ranges, dir == 0 ? 1 : 0, X.ncls, a.pos_end);
   a.nxcls = X.ncls;
+  a.nblocks = (D.nlines + 3) / 4;
   a.nmix = 0;
-  for (int q = 0; q < 3; ++q) {
-    const int e = a.line_end[q];
-    if (e <= 0 || e >= D.nlines || e % 4 == 0) continue;
-    const int blk = e / 4;
-    bool seen = false;
-    for (int m = 0; m < a.nmix; ++m) seen = seen || a.mix[m] == blk;
-    if (!seen) a.mix[a.nmix++] = blk;
+  if (dir == 0) {
+    // r sweep: row groups that straddle a band boundary, one row per workgroup
+    for (int q = 0; q < 3; ++q) {
+      const int e = a.line_end[q];
+      if (e <= 0 || e >= D.nlines || e % 4 == 0) continue;
+      bool seen = false;
+      for (int m = 0; m < a.nmix; ++m) seen = seen || a.mix[m] == e / 4;
+      if (!seen) a.mix[a.nmix++] = e / 4;
+    }
   }
   for (int m = a.nmix; m < 4; ++m) a.mix[m] = -1;
   const StripVariant& V = kStrip[D.L.variant];

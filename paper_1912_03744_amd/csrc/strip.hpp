@@ -39,21 +39,17 @@ struct StripArgs {
   long strip;               // doubles per strip
   int nr, nz;
   int nlines;               // lines of this direction
-  int nblocks;              // strips (z sweep) or row groups (r sweep)
   int line_end[3];          // class of line l: number of q with l >= line_end[q]
   int pos_end[3];           // crossing class of position p: number of q with p >= pos_end[q]
   int nxcls;                // crossing classes
-  int nmix;                 // blocks whose 4 lines are not all of one class ...
-  int mix[4];               // ... solved one line per workgroup by nblocks + 4*m + line
+  int nblocks;              // row groups (r sweep)
+  int nmix;                 // r sweep: row groups whose rows are not all of one band ...
+  int mix[4];               // ... solved one row per workgroup by nblocks + 4*m + row
 };
 
-__device__ __forceinline__ int class_at(const int* ends, int x) {
-  return (x >= ends[0]) + (x >= ends[1]) + (x >= ends[2]);
-}
-
-// Which block and which of its lines a workgroup takes: b < nblocks is block
-// b with all its lines (lc = -1) unless the block is mixed (then nothing);
-// b >= nblocks is line lc of mixed block mix[(b - nblocks) / 4].
+// r sweep work of a workgroup: b < nblocks is row group b with all its rows
+// (lc = -1) unless the group is mixed (then nothing); b >= nblocks is row lc
+// of mixed group mix[(b - nblocks) / 4].
 __device__ __forceinline__ bool strip_work(const StripArgs& a, int b, int* blk, int* lc) {
   if (b < a.nblocks) {
     for (int m = 0; m < a.nmix; ++m)
@@ -67,56 +63,83 @@ __device__ __forceinline__ bool strip_work(const StripArgs& a, int b, int* blk, 
   return true;
 }
 
-// Crossing constants of the block's lines: xcv[c][r] for crossing class c
-// and line line0 + r (uniform across the workgroup).
-template <int R>
-__device__ __forceinline__ void load_crossing(const StripArgs& a, int line0, int nact, double (*xcv)[R]) {
-#pragma unroll
-  for (int c = 0; c < MAX_CLS; ++c)
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      xcv[c][r] = (c < a.nxcls && r < nact) ? a.xc[(long)c * a.nlines + line0 + r] : 0.0;
+__device__ __forceinline__ int class_at(const int* ends, int x) {
+  return (x >= ends[0]) + (x >= ends[1]) + (x >= ends[2]);
 }
 
-template <int M, int R>
-__device__ __forceinline__ void add_crossing(const StripArgs& a, double (*o)[M], const double (*xcv)[R],
-                                             unsigned long long live, int p0) {
+// Add the crossing constants of the other direction to the outputs of the
+// lines in `mask`: for line line0 + r at position p, xc[class of p][line]
+// (uniform across the workgroup), at positions inside the domain.
+template <int M>
+__device__ __forceinline__ void add_crossing(const StripArgs& a, double (*o)[M], int line0, unsigned mask,
+                                             int n, int p0) {
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
-    if (!((live >> t) & 1ull)) continue;
-    const int c = class_at(a.pos_end, p0 + t);
+  for (int r = 0; r < 4; ++r) {
+    if (!((mask >> r) & 1u)) continue;
+    double xcv[MAX_CLS];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      o[r][t] += c == 0 ? xcv[0][r] : (c == 1 ? xcv[1][r] : (c == 2 ? xcv[2][r] : xcv[3][r]));
+    for (int c = 0; c < MAX_CLS; ++c) xcv[c] = c < a.nxcls ? a.xc[(long)c * a.nlines + line0 + r] : 0.0;
+    const LineTab& tb = a.tabs[class_at(a.line_end, line0 + r)];
+    const unsigned long long live = chunk_live_mask(p0, M, n, tb.skip_lo, tb.skip_hi);
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      const int c = class_at(a.pos_end, p0 + t);
+      if ((live >> t) & 1ull) o[r][t] += c == 0 ? xcv[0] : (c == 1 ? xcv[1] : (c == 2 ? xcv[2] : xcv[3]));
+    }
+  }
+}
+
+// Solve the 4 lines of a block and hand each line's outputs to `emit`
+// (v: solution, o: next right-hand side, mask of the lines to take).  Lines
+// of one class are solved together; a block whose lines span several classes
+// (classes grow with the line index) is solved once per class, each pass
+// refetching the block's right-hand side with `fetch`.  L: the tables of the
+// first class, already loaded; later passes reload it.
+template <int M, int NW, class Fetch, class Emit>
+__device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], int line0, int nact, int n,
+                                            double* carry, LaneTab<M>& L, Fetch fetch, Emit emit) {
+  const int tid = threadIdx.x;
+  const int p0 = tid * M;
+  const int c_lo = class_at(a.line_end, line0), c_hi = class_at(a.line_end, line0 + nact - 1);
+  auto lines_of = [&](int c) {
+    unsigned mine = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r < nact && class_at(a.line_end, line0 + r) == c) mine |= 1u << r;
+    return mine;
+  };
+  for (int c = c_lo; c <= c_hi; ++c) {
+    const LineTab& tb = a.tabs[c];
+    if (c > c_lo) {
+      load_lanetab<M, 64 * NW>(L, tb.pos + tid, tb.chk + tid);  // L held the first class
+      fetch(v);
+    }
+    double o[4][M];
+    solve_lanes<M, NW, 4>(v, o, L, chunk_live_mask(p0, M, n, tb.skip_lo, tb.skip_hi), carry);
+    emit(v, o, lines_of(c));
   }
 }
 
 // z sweep: workgroup per strip (4 adjacent columns), lane k holds rows
-// [kM, kM+M) of the strip's columns.
+// [kM, kM+M) of the strip's columns.  Each lane reads and writes only its
+// own chunk's LDS slots between the staging copies.
 template <int M, int NW>
 __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
   constexpr int NT = 64 * NW;
   constexpr int CH = 4 * M;  // LDS doubles per chunk
-  // The staged strip takes exactly 64*NW*4*M doubles (80 KB for a 2560-row
-  // strip), so that two workgroups fit in one compute unit's LDS; the
-  // solver's carries live in the same buffer while the data sit in
-  // registers.
   __shared__ __align__(16) double buf[NT * CH];
-  double* carry = buf;
-  static_assert(NT * CH >= NW * 5, "carry slots");
-  int s, lc;
-  if (!strip_work(a, xcd_block(blockIdx.x, gridDim.x), &s, &lc)) return;
+  __shared__ double carry[2 * NW * 5];
+  const int s = xcd_block(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int c0 = 4 * s;
   const int nact = min(4, a.nr - c0);
-  if (lc >= nact) return;
-  const int line0 = lc < 0 ? c0 : c0 + lc;
-  const LineTab& tb = a.tabs[class_at(a.line_end, line0)];
   const int p0 = tid * M;
-  LaneTab<M> L;
-  load_lanetab<M, NT>(L, tb.pos + tid, tb.chk + tid);
-  const unsigned long long live = chunk_live_mask(p0, M, a.nz, tb.skip_lo, tb.skip_hi);
-
+  // factor tables of the first class ahead of the data
+  LaneTab<M> L0;
+  {
+    const LineTab& tb = a.tabs[class_at(a.line_end, c0)];
+    load_lanetab<M, NT>(L0, tb.pos + tid, tb.chk + tid);
+  }
   const double2* __restrict__ src = (const double2*)(a.din + (long)s * a.strip);
 #pragma unroll
   for (int u = 0; u < 2 * M; ++u) {
@@ -128,76 +151,71 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
     *(double2*)&buf[kk * CH + t * 4 + (q & 1) * 2] = x;
   }
   __syncthreads();
-  if (lc < 0) {
-    double v[4][M], o[4][M];
+  double* mine_slots = buf + tid * CH;
+  auto fetch = [&](double (*v)[M]) {
 #pragma unroll
     for (int t = 0; t < M; ++t) {
-      const double2 lo = *(const double2*)&buf[tid * CH + t * 4];
-      const double2 hi = *(const double2*)&buf[tid * CH + t * 4 + 2];
+      const double2 lo = *(const double2*)&mine_slots[t * 4];
+      const double2 hi = *(const double2*)&mine_slots[t * 4 + 2];
       v[0][t] = lo.x; v[1][t] = lo.y; v[2][t] = hi.x; v[3][t] = hi.y;
     }
-    __syncthreads();  // buf is reused for the outputs
-    solve_lanes<M, NW, 4>(v, o, L, live, carry);
-    if (a.xc) {
-      double xcv[MAX_CLS][4];
-      load_crossing<4>(a, line0, nact, xcv);
-      add_crossing<M, 4>(a, o, xcv, live, p0);
-    }
+  };
+  auto emit = [&](double (*v)[M], double (*o)[M], unsigned mask) {
+    if (a.xc) add_crossing<M>(a, o, c0, mask, a.nz, p0);
+    if (mask == 0xfu) {
 #pragma unroll
-    for (int t = 0; t < M; ++t) {
-      *(double2*)&buf[tid * CH + t * 4] = make_double2(o[0][t], nact > 1 ? o[1][t] : 0.0);
-      *(double2*)&buf[tid * CH + t * 4 + 2] = make_double2(nact > 2 ? o[2][t] : 0.0, nact > 3 ? o[3][t] : 0.0);
-    }
-    __syncthreads();
-    double2* __restrict__ dst = (double2*)(a.dout + (long)s * a.strip);
-#pragma unroll
-    for (int u = 0; u < 2 * M; ++u) {
-      const int q = tid + u * NT;
-      const int j = q >> 1;
-      if (j < a.nz) {
-        const int kk = j / M, t = j - kk * M;
-        dst[q] = *(const double2*)&buf[kk * CH + t * 4 + (q & 1) * 2];
+      for (int t = 0; t < M; ++t) {
+        *(double2*)&mine_slots[t * 4] = make_double2(o[0][t], o[1][t]);
+        *(double2*)&mine_slots[t * 4 + 2] = make_double2(o[2][t], o[3][t]);
       }
+    } else {
+#pragma unroll
+      for (int t = 0; t < M; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if ((mask >> r) & 1u) mine_slots[t * 4 + r] = o[r][t];
     }
-    if (a.xout) {
+    if (a.xout)
 #pragma unroll
       for (int t = 0; t < M; ++t)
         if (p0 + t < a.nz)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            if (c < nact) a.xout[(long)(p0 + t) * a.nr + c0 + c] = v[c][t];
-    }
-  } else {
-    // one line of a mixed strip: column lc with its own class
-    double v[1][M], o[1][M];
+            if ((mask >> c) & 1u) a.xout[(long)(p0 + t) * a.nr + c0 + c] = v[c][t];
+  };
+  double v[4][M];
+  fetch(v);
+  // columns past the grid's edge hold 0
 #pragma unroll
-    for (int t = 0; t < M; ++t) v[0][t] = buf[tid * CH + t * 4 + lc];
-    __syncthreads();  // the carries overwrite buf
-    solve_lanes<M, NW, 1>(v, o, L, live, carry);
-    if (a.xc) {
-      double xcv[MAX_CLS][1];
-      load_crossing<1>(a, line0, 1, xcv);
-      add_crossing<M, 1>(a, o, xcv, live, p0);
-    }
-    double* __restrict__ dst = a.dout + (long)s * a.strip + lc;
+  for (int t = 0; t < M; ++t)
 #pragma unroll
-    for (int t = 0; t < M; ++t)
-      if (p0 + t < a.nz) {
-        dst[4L * (p0 + t)] = o[0][t];
-        if (a.xout) a.xout[(long)(p0 + t) * a.nr + line0] = v[0][t];
-      }
+    for (int r = 0; r < 4; ++r)
+      if (r >= nact) mine_slots[t * 4 + r] = 0.0;
+  solve_block<M, NW>(a, v, c0, nact, a.nz, carry, L0, fetch, emit);
+  __syncthreads();
+  double2* __restrict__ dst = (double2*)(a.dout + (long)s * a.strip);
+#pragma unroll
+  for (int u = 0; u < 2 * M; ++u) {
+    const int q = tid + u * NT;
+    const int j = q >> 1;
+    if (j < a.nz) {
+      const int kk = j / M, t = j - kk * M;
+      dst[q] = *(const double2*)&buf[kk * CH + t * 4 + (q & 1) * 2];
+    }
   }
 }
 
 // r sweep: workgroup per group of 4 consecutive rows, lane k holds columns
-// [4k, 4k+4) of the rows: exactly tile k of the row group.
+// [4k, 4k+4) of the rows: exactly tile k of the row group, in its own LDS
+// slots.  Row groups that straddle a band boundary are solved one row per
+// workgroup (extra workgroups of the same launch).
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
   constexpr int M = 4;
   constexpr int NT = 64 * NW;
   constexpr int CH = 18;  // a 16-double tile + 2 pad
   __shared__ __align__(16) double buf[NT * CH];
-  __shared__ double carry[NW * 5];
+  __shared__ double carry[2 * NW * 5];
   int J, lc;
   if (!strip_work(a, xcd_block(blockIdx.x, gridDim.x), &J, &lc)) return;
   const int tid = threadIdx.x;
@@ -220,26 +238,23 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
     *(double2*)&buf[st * CH + (q & 7) * 2] = x;
   }
   __syncthreads();
+  double* mine_slots = buf + tid * CH;
   if (lc < 0) {
     double v[4][M], o[4][M];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const double2 lo = *(const double2*)&buf[tid * CH + r * 4];
-      const double2 hi = *(const double2*)&buf[tid * CH + r * 4 + 2];
+      const double2 lo = *(const double2*)&mine_slots[r * 4];
+      const double2 hi = *(const double2*)&mine_slots[r * 4 + 2];
       v[r][0] = lo.x; v[r][1] = lo.y; v[r][2] = hi.x; v[r][3] = hi.y;
     }
-    __syncthreads();
     solve_lanes<M, NW, 4>(v, o, L, live, carry);
-    if (a.xc) {
-      double xcv[MAX_CLS][4];
-      load_crossing<4>(a, line0, nact, xcv);
-      add_crossing<M, 4>(a, o, xcv, live, p0);
-    }
+    const unsigned mask = nact == 4 ? 0xfu : (1u << nact) - 1u;
+    if (a.xc) add_crossing<M>(a, o, j0, mask, a.nr, p0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const bool on = r < nact;
-      *(double2*)&buf[tid * CH + r * 4] = make_double2(on ? o[r][0] : 0.0, on ? o[r][1] : 0.0);
-      *(double2*)&buf[tid * CH + r * 4 + 2] = make_double2(on ? o[r][2] : 0.0, on ? o[r][3] : 0.0);
+      *(double2*)&mine_slots[r * 4] = make_double2(on ? o[r][0] : 0.0, on ? o[r][1] : 0.0);
+      *(double2*)&mine_slots[r * 4 + 2] = make_double2(on ? o[r][2] : 0.0, on ? o[r][3] : 0.0);
     }
     __syncthreads();
 #pragma unroll
@@ -263,12 +278,15 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
     // one row of a mixed row group
     double v[1][M], o[1][M];
 #pragma unroll
-    for (int t = 0; t < M; ++t) v[0][t] = buf[tid * CH + lc * 4 + t];
+    for (int t = 0; t < M; ++t) v[0][t] = mine_slots[lc * 4 + t];
     solve_lanes<M, NW, 1>(v, o, L, live, carry);
     if (a.xc) {
-      double xcv[MAX_CLS][1];
-      load_crossing<1>(a, line0, 1, xcv);
-      add_crossing<M, 1>(a, o, xcv, live, p0);
+      double o4[4][M];
+#pragma unroll
+      for (int t = 0; t < M; ++t) o4[0][t] = o[0][t], o4[1][t] = o4[2][t] = o4[3][t] = 0.0;
+      add_crossing<M>(a, o4, line0, 1u, a.nr, p0);
+#pragma unroll
+      for (int t = 0; t < M; ++t) o[0][t] = o4[0][t];
     }
     if (tid < nstrips) {
       double* __restrict__ d = a.dout + (long)tid * a.strip + (long)line0 * 4;
