@@ -22,6 +22,8 @@ Prints one JSON line:
               in one persistent launch, autotuned; cell-updates/s and the
               kernel's algorithmic bandwidth (32 B per active cell per step)
 Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 200] [--no-batch]
+       python bench.py --counter-workload          (the program profiled for traffic)
+       python bench.py --summarize-counters DIR    (rocprofv3 --pmc output -> profiles/)
 """
 from __future__ import annotations
 
@@ -109,7 +111,85 @@ def batch_leg(n, steps, tune=True):
     return out
 
 
+COUNTER_COPY_BYTES = 64 << 20
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "sweep_counters_production_1024x2560.json")
+
+
+def counter_workload(seed):
+    """The program profiled for HBM traffic (one rocprofv3 --pmc pass per
+    counter): a plain copy of COUNTER_COPY_BYTES (torch.neg, read once and
+    written once) to calibrate the counters, then 20 launches of each sweep
+    of the production grid in the benchmark's layout and shapes."""
+    import torch
+
+    from paper_1912_03744_amd import autotune, native
+    from paper_1912_03744_amd import workloads as W
+    torch.cuda.set_device(0)
+    src = torch.ones(COUNTER_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    spec = W.production(seed)
+    p = native.Problem.from_spec(spec)
+    autotune.apply(p, spec.dt, spec.scheme)
+    p.step(spec.dt, 2)
+    p.time_sweeps(spec.dt, 20)
+    print("counter workload done: layout %s r %s z %s" % (p.layout(), p.get_launch(0), p.get_launch(1)), flush=True)
+
+
+def summarize_counters(root):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the sweeps from two
+    rocprofv3 --pmc runs of counter_workload (root/fetch, root/write), scaled
+    by what the same counters read for the calibration copy, into
+    COUNTERS_JSON."""
+    import csv
+    import glob
+    import re
+
+    def means(pattern):
+        out = {}
+        files = glob.glob(os.path.join(root, pattern, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit("no counter_collection.csv under %s" % os.path.join(root, pattern))
+        for f in files:
+            for row in csv.DictReader(open(f)):
+                k = row["Kernel_Name"]
+                if "neg" in k:
+                    name = "copy"
+                elif re.search(r"k_sweep_rs", k):
+                    name = "sweep_r"
+                elif re.search(r"k_sweep_zs|k_sweepILi", k):
+                    name = "sweep_z" if "zs" in k else "sweep_rows"
+                else:
+                    continue
+                out.setdefault(name, []).append(float(row["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in out.items()}
+    fetch, write = means("fetch"), means("write")
+    f_scale = COUNTER_COPY_BYTES / (fetch["copy"] * 1024.0)
+    w_scale = COUNTER_COPY_BYTES / (write["copy"] * 1024.0)
+    rec = {"source_digest": source_digest(),
+           "calibration": {"copy_bytes": COUNTER_COPY_BYTES, "copy_fetch_kib": fetch["copy"],
+                           "copy_write_kib": write["copy"], "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernels": {}}
+    for k in ("sweep_r", "sweep_z"):
+        if k in fetch and k in write:
+            fb = fetch[k] * 1024.0 * f_scale
+            wb = write[k] * 1024.0 * w_scale
+            rec["kernels"][k] = {"fetch_kib": fetch[k], "write_kib": write[k], "fetch_bytes": fb,
+                                 "write_bytes": wb, "hbm_bytes_per_launch": fb + wb}
+    with open(COUNTERS_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--counter-workload":
+        counter_workload(0)
+        return
+    if len(sys.argv) > 2 and sys.argv[1] == "--summarize-counters":
+        summarize_counters(sys.argv[2])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10_000)

@@ -190,6 +190,9 @@ adi_status adi_layout_shapes(int32_t layout, int32_t dir, int32_t* out, int32_t 
 adi_status adi_set_layout(adi_problem p, int32_t layout);
 adi_status adi_get_layout(adi_problem p, int32_t* layout);
 
+/* Wait until all work enqueued on the problem's stream has finished. */
+adi_status adi_sync(adi_problem p);
+
 /* Steps per captured HIP graph in adi_step (0 = plain launches). */
 adi_status adi_set_graph_steps(adi_problem p, int32_t steps);
 
@@ -281,6 +284,9 @@ adi_status adi_mlp_set_params(adi_mlp m, const float* host_in, int64_t count);
  * widths[last]] fp32 are device pointers; batch is a multiple of 64.
  * Asynchronous on the network's stream. */
 adi_status adi_mlp_forward(adi_mlp m, const float* dev_x, int64_t batch, float* dev_y);
+
+/* Wait until all work enqueued on the network's stream has finished. */
+adi_status adi_mlp_sync(adi_mlp m);
 
 /* Mean-squared-error loss against dev_t and its gradient w.r.t. every
  * parameter (copied to host_grads, nullable); loss_out (host, nullable).

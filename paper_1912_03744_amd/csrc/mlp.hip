@@ -536,6 +536,12 @@ adi_status adi_mlp_forward(adi_mlp m, const float* dev_x, int64_t batch, float* 
   return ADI_OK;
 }
 
+adi_status adi_mlp_sync(adi_mlp m) {
+  ADI_TRY(mlp_handle(m));
+  ADI_HIP(hipStreamSynchronize(m->stream));
+  return ADI_OK;
+}
+
 adi_status adi_mlp_gradients(adi_mlp m, const float* dev_x, const float* dev_t, int64_t batch, float* host_grads,
                              float* loss_out) {
   ADI_TRY(mlp_handle(m));

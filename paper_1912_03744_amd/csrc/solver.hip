@@ -1110,6 +1110,12 @@ adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lin
   return ADI_OK;
 }
 
+adi_status adi_sync(adi_problem p) {
+  ADI_TRY(check_handle(p));
+  ADI_HIP(hipStreamSynchronize(p->stream));
+  return ADI_OK;
+}
+
 adi_status adi_set_layout(adi_problem p, int32_t layout) {
   ADI_TRY(check_handle(p));
   if (layout != ADI_LAYOUT_ROWS && layout != ADI_LAYOUT_STRIPS)

@@ -83,6 +83,8 @@ _SIGS = {
     "adi_launch_shapes": [_i32p, ctypes.c_int32, _i32p],
     "adi_layout_shapes": [ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int32, _i32p],
     "adi_set_layout": [_vp, ctypes.c_int32],
+    "adi_sync": [_vp],
+    "adi_mlp_sync": [_vp],
     "adi_get_layout": [_vp, _i32p],
     "adi_destroy": [_vp],
     "adi_create_batch": [ctypes.c_int32, ctypes.POINTER(Geometry), ctypes.POINTER(BC), ctypes.c_int,
@@ -153,6 +155,10 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(_dp)
 
 
+def _torch_stream_sync():
+    torch.cuda.current_stream().synchronize()
+
+
 def current_stream():
     """The current torch stream as a hipStream_t, or None (the library then
     uses a stream of its own) when torch has no GPU or is on its default
@@ -180,6 +186,8 @@ class Problem:
         check(lib().adi_create_problem(ctypes.byref(g), ctypes.byref(bc), SCHEMES[scheme], st,
                                        ctypes.byref(h_)))
         self._h = h_
+        # on a stream of its own the library is not ordered with torch's work
+        self._own_stream = st is None
         self._destroy = lib().adi_destroy
         self.scheme = scheme
 
@@ -230,7 +238,14 @@ class Problem:
         return out
 
     def read_field_device(self, dev_ptr):
+        """Copy T into device memory at dev_ptr (nz*nr doubles).  On the
+        problem's stream; when that is a stream of the library's own, the
+        call waits for torch's current stream first and for the copy after."""
+        if self._own_stream:
+            _torch_stream_sync()
         check(lib().adi_read_field_device(self._h, ctypes.c_void_p(dev_ptr)))
+        if self._own_stream:
+            check(lib().adi_sync(self._h))
 
     def region_map(self):
         out = np.empty(self.shape, dtype=np.uint8)
@@ -372,6 +387,9 @@ class MLP:
         st = stream if stream is not None else current_stream()
         check(lib().adi_mlp_create(w, len(widths), int(seed), st, ctypes.byref(h)))
         self._h = h
+        # on a stream of its own the library is not ordered with torch's
+        # work: calls that take torch tensors then synchronise both sides
+        self._own_stream = st is None
         self._destroy = lib().adi_mlp_destroy
         self.widths = [int(x) for x in widths]
         n = ctypes.c_int64()
@@ -412,22 +430,35 @@ class MLP:
             o += b
         return out
 
+    def _before(self):
+        if self._own_stream:
+            _torch_stream_sync()
+
+    def _after(self):
+        if self._own_stream:
+            check(lib().adi_mlp_sync(self._h))
+
     def forward(self, x, y):
         """x, y: contiguous torch float32 cuda tensors [B, n_in] / [B, n_out]."""
+        self._before()
         check(lib().adi_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
                                     ctypes.c_void_p(y.data_ptr())))
+        self._after()
 
     def gradients(self, x, t):
         g = np.empty(self.nparams, dtype=np.float32)
         loss = ctypes.c_float()
+        self._before()
         check(lib().adi_mlp_gradients(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
                                       int(x.shape[0]), g.ctypes.data_as(_fp), ctypes.byref(loss)))
         return g, loss.value
 
     def train_step(self, x, t, lr, want_loss=False):
         loss = ctypes.c_float()
+        self._before()
         check(lib().adi_mlp_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
                                        int(x.shape[0]), float(lr), ctypes.byref(loss) if want_loss else None))
+        self._after()
         return loss.value if want_loss else None
 
 
