@@ -686,31 +686,32 @@ struct LaneTab {
   double cs, ae, W0, Q0, C0, W1, Q1, C1, cprev;
 };
 
-// pos/chk: class tables already offset by the lane's chunk k; G chunks.
+// pos/chk: the class tables (uniform across the workgroup), k: the lane's
+// chunk, G chunks.  Every load is a uniform base plus the lane offset k.
 template <int M, int G>
-__device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, const double* chk_) {
+__device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, const double* chk_, int k) {
   constexpr int GM = G * M;
   const gptr pos = (gptr)pos_;
   const gptr chk = (gptr)chk_;
 #pragma unroll
   for (int t = 1; t <= M - 2; ++t) {
-    L.w[t] = pos[P_W * GM + t * G];
-    L.qa[t] = pos[P_QA * GM + t * G];
-    L.cp[t] = pos[P_CP * GM + t * G];
-    L.sp[t] = pos[P_SP * GM + t * G];
-    L.sr[t] = pos[P_SR * GM + t * G];
+    L.w[t] = pos[P_W * GM + t * G + k];
+    L.qa[t] = pos[P_QA * GM + t * G + k];
+    L.cp[t] = pos[P_CP * GM + t * G + k];
+    L.sp[t] = pos[P_SP * GM + t * G + k];
+    L.sr[t] = pos[P_SR * GM + t * G + k];
   }
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    L.od[t] = pos[P_OD * GM + t * G];
-    L.ol[t] = pos[P_OL * GM + t * G];
-    L.ou[t] = pos[P_OU * GM + t * G];
-    L.oc[t] = pos[P_OC * GM + t * G];
+    L.od[t] = pos[P_OD * GM + t * G + k];
+    L.ol[t] = pos[P_OL * GM + t * G + k];
+    L.ou[t] = pos[P_OU * GM + t * G + k];
+    L.oc[t] = pos[P_OC * GM + t * G + k];
   }
-  L.cs = chk[C_CS * G]; L.ae = chk[C_AE * G];
-  L.W0 = chk[C_W0 * G]; L.Q0 = chk[C_Q0 * G]; L.C0 = chk[C_C0 * G];
-  L.W1 = chk[C_W1 * G]; L.Q1 = chk[C_Q1 * G]; L.C1 = chk[C_C1 * G];
-  L.cprev = chk[C_CPREV * G];
+  L.cs = chk[C_CS * G + k]; L.ae = chk[C_AE * G + k];
+  L.W0 = chk[C_W0 * G + k]; L.Q0 = chk[C_Q0 * G + k]; L.C0 = chk[C_C0 * G + k];
+  L.W1 = chk[C_W1 * G + k]; L.Q1 = chk[C_Q1 * G + k]; L.C1 = chk[C_C1 * G + k];
+  L.cprev = chk[C_CPREV * G + k];
 }
 
 // ---- wavefront scans of affine maps (x_k = A_k + B_k x_{k-1}) with DPP ----
@@ -726,6 +727,16 @@ __device__ __forceinline__ double dpp_row(double old, double src) {
   const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
   const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP broadcast across rows (row_bcast:15 / row_bcast:31), writing only the
+// rows in ROWS; other lanes keep `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast(double old, double src) {
+  const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROWS, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -749,26 +760,17 @@ __device__ __forceinline__ void wave_scan_fwd(double (&F)[R], double& B) {
   }
   ADI_FWD_STEP(1) ADI_FWD_STEP(2) ADI_FWD_STEP(4) ADI_FWD_STEP(8)
 #undef ADI_FWD_STEP
-  // row totals at lanes 15, 31, 47; prefix of the rows below each row
-  const int row = lane >> 4;
-  double cF[R], cB = 1.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) cF[r] = 0.0;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const double tB = read_lane(B, 16 * q + 15);
-    double tF[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) tF[r] = read_lane(F[r], 16 * q + 15);
-    if (row > q) {  // compose: row total q after the prefix so far
-#pragma unroll
-      for (int r = 0; r < R; ++r) cF[r] = tF[r] + tB * cF[r];
-      cB *= tB;
-    }
+  // across rows: row_bcast:15 hands the last lane of rows 0 and 2 to rows 1
+  // and 3, then row_bcast:31 hands lane 31 to rows 2 and 3
+#define ADI_FWD_BCAST(CTRL, ROWS)                                                        \
+  {                                                                                     \
+    const double Bo = dpp_bcast<CTRL, ROWS>(1.0, B);                                    \
+    _Pragma("unroll") for (int r = 0; r < R; ++r) F[r] += B * dpp_bcast<CTRL, ROWS>(0.0, F[r]); \
+    B *= Bo;                                                                            \
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r) F[r] += B * cF[r];
-  B *= cB;
+  ADI_FWD_BCAST(0x142, 0xa) ADI_FWD_BCAST(0x143, 0xc)
+#undef ADI_FWD_BCAST
+  (void)lane;
 }
 
 // Inclusive backward scan (x_k = H_k + E_k x_{k+1}): lane k ends with the
@@ -813,8 +815,8 @@ __device__ __forceinline__ void wave_scan_bwd(double (&U)[R], double& E) {
 // precomputed factors, reduced system by recursive doubling over the chunks,
 // back substitution), with data and factors already in registers.  On
 // return v holds the solution and o the next half step's right-hand side
-// without the crossing constants, 0 outside the domain.  `lds` holds
-// 2*NW*(R+1) doubles.  Every lane of the workgroup must call this (it
+// without the crossing constants (0 outside the domain, given a right-hand
+// side that is 0 there).  `lds` holds 2*NW*(R+1) doubles.  Every lane of the workgroup must call this (it
 // contains barriers when NW > 1).
 template <int M, int NW, int R>
 __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], const LaneTab<M>& L,
@@ -823,11 +825,10 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
 
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int t = 0; t < M; ++t)
-      if (!((live >> t) & 1ull)) v[r][t] = 0.0;
+  // Cells outside the domain and past the line's end are identity rows with
+  // a zero output operator and carry exactly 0 in every right-hand side, so
+  // they solve to 0 and produce 0 without masking.
+  (void)live;
 
   // interior forward elimination and back substitution (rows 1..M-2)
   double run[R];
@@ -933,16 +934,13 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
 
   // next half step's right-hand side
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
-    const bool lv = (live >> t) & 1ull;
+  for (int t = 0; t < M; ++t)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double xl = t > 0 ? v[r][t > 0 ? t - 1 : 0] : xm1[r];
       const double xr = t < M - 1 ? v[r][t < M - 1 ? t + 1 : t] : xp1[r];
-      const double y = L.od[t] * v[r][t] + L.ol[t] * xl + L.ou[t] * xr + L.oc[t];
-      o[r][t] = lv ? y : 0.0;
+      o[r][t] = L.od[t] * v[r][t] + L.ol[t] * xl + L.ou[t] * xr + L.oc[t];
     }
-  }
 }
 
 }  // namespace adi

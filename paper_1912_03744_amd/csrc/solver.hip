@@ -103,21 +103,36 @@ __global__ void __launch_bounds__(256) k_assemble(Params P, Geom g, DirTabs r, D
 }
 
 // Right-hand side of the first r half step from a field T: the z-direction
-// output operator applied to T plus the r boundary constant.
+// output operator applied to T plus the r boundary constant.  Every element
+// of the buffer is written: cells outside the domain and padding get exactly
+// 0, which the strip sweeps rely on.  strip = 0: rows layout (nr*nz
+// elements); else strip layout with `total` elements.
 __global__ void k_init_rhs(const double* __restrict__ T, double* __restrict__ d, Geom g,
-                           DirTabs z, const double* __restrict__ rxc, int nr, int nz, long strip) {
-  const long n = (long)nr * nz;
-  for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n; c += (long)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nr), j = (int)(c / nr);
-    const int kap = g.kap[i], bet = g.bet[j];
-    if (region_of(bet, kap) == MASKED) continue;
-    const long GM = (long)z.G * z.M;
-    const double* pos = z.pos + kap * P_NFIELDS * GM;
-    const long ix = (long)(j % z.M) * z.G + j / z.M;
-    double o = pos[P_OD * GM + ix] * T[c] + pos[P_OC * GM + ix] + rxc[(long)bet * nr + i];
-    if (j > 0) o += pos[P_OL * GM + ix] * T[c - nr];
-    if (j < nz - 1) o += pos[P_OU * GM + ix] * T[c + nr];
-    d[strip ? (long)(i >> 2) * strip + 4L * j + (i & 3) : c] = o;
+                           DirTabs z, const double* __restrict__ rxc, int nr, int nz, long strip, long total) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    int i, j;
+    if (strip) {
+      const long s = e / strip, rem = e - s * strip;
+      j = (int)(rem >> 2);
+      i = (int)(4 * s + (rem & 3));
+    } else {
+      i = (int)(e % nr);
+      j = (int)(e / nr);
+    }
+    double o = 0.0;
+    if (i < nr && j < nz) {
+      const int kap = g.kap[i], bet = g.bet[j];
+      if (region_of(bet, kap) != MASKED) {
+        const long c = (long)j * nr + i;
+        const long GM = (long)z.G * z.M;
+        const double* pos = z.pos + kap * P_NFIELDS * GM;
+        const long ix = (long)(j % z.M) * z.G + j / z.M;
+        o = pos[P_OD * GM + ix] * T[c] + pos[P_OC * GM + ix] + rxc[(long)bet * nr + i];
+        if (j > 0) o += pos[P_OL * GM + ix] * T[c - nr];
+        if (j < nz - 1) o += pos[P_OU * GM + ix] * T[c + nr];
+      }
+    }
+    d[e] = o;
   }
 }
 
@@ -543,8 +558,10 @@ adi_status ensure_tables(adi_problem p, double dt) {
 adi_status launch_init_rhs(adi_problem p) {
   const long n = (long)p->P.nr * p->P.nz;
   const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+  const bool strips = p->layout == ADI_LAYOUT_STRIPS;
+  const long total = strips ? (long)((p->P.nr + 3) / 4) * p->strip : n;
   hipLaunchKernelGGL(k_init_rhs, dim3(blocks), dim3(256), 0, p->stream, p->T, p->dA, p->g, p->z.view(),
-                     p->r.xc, p->P.nr, p->P.nz, p->layout == ADI_LAYOUT_STRIPS ? p->strip : 0L);
+                     p->r.xc, p->P.nr, p->P.nz, strips ? p->strip : 0L, total);
   ADI_CHECK_LAUNCH();
   p->rhs_valid = true;
   return ADI_OK;

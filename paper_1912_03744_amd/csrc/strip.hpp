@@ -63,6 +63,15 @@ __device__ __forceinline__ bool strip_work(const StripArgs& a, int b, int* blk, 
   return true;
 }
 
+// Orders LDS accesses among the lanes of one wave (no workgroup barrier):
+// staging copies are per wave, so waves proceed independently until the
+// solver's carries.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int class_at(const int* ends, int x) {
   return (x >= ends[0]) + (x >= ends[1]) + (x >= ends[2]);
 }
@@ -111,7 +120,7 @@ __device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], 
   for (int c = c_lo; c <= c_hi; ++c) {
     const LineTab& tb = a.tabs[c];
     if (c > c_lo) {
-      load_lanetab<M, 64 * NW>(L, tb.pos + tid, tb.chk + tid);  // L held the first class
+      load_lanetab<M, 64 * NW>(L, tb.pos, tb.chk, tid);  // L held the first class
       fetch(v);
     }
     double o[4][M];
@@ -122,7 +131,8 @@ __device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], 
 
 // z sweep: workgroup per strip (4 adjacent columns), lane k holds rows
 // [kM, kM+M) of the strip's columns.  Each lane reads and writes only its
-// own chunk's LDS slots between the staging copies.
+// own chunk's LDS slots between the staging copies, which each wave does for
+// its own chunks.
 template <int M, int NW>
 __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
   constexpr int NT = 64 * NW;
@@ -138,19 +148,23 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
   LaneTab<M> L0;
   {
     const LineTab& tb = a.tabs[class_at(a.line_end, c0)];
-    load_lanetab<M, NT>(L0, tb.pos + tid, tb.chk + tid);
+    load_lanetab<M, NT>(L0, tb.pos, tb.chk, tid);
   }
-  const double2* __restrict__ src = (const double2*)(a.din + (long)s * a.strip);
+  // each wave stages the 64*M rows of its own 64 chunks (contiguous in the
+  // strip) through its own LDS region
+  const int lane = tid & 63, wrow0 = (tid >> 6) * 64 * M;
+  double* wbuf = buf + (tid >> 6) * 64 * CH;
+  const double2* __restrict__ src = (const double2*)(a.din + (long)s * a.strip) + 2 * wrow0;
 #pragma unroll
   for (int u = 0; u < 2 * M; ++u) {
-    const int q = tid + u * NT;  // row q/2, column pair q%2
-    const int j = q >> 1;
+    const int q = lane + u * 64;  // local row q/2, column pair q%2
+    const int jl = q >> 1;
     double2 x = make_double2(0.0, 0.0);
-    if (j < a.nz) x = src[q];
-    const int kk = j / M, t = j - kk * M;
-    *(double2*)&buf[kk * CH + t * 4 + (q & 1) * 2] = x;
+    if (wrow0 + jl < a.nz) x = src[q];
+    const int kk = jl / M, t = jl - kk * M;
+    *(double2*)&wbuf[kk * CH + t * 4 + (q & 1) * 2] = x;
   }
-  __syncthreads();
+  wave_sync();
   double* mine_slots = buf + tid * CH;
   auto fetch = [&](double (*v)[M]) {
 #pragma unroll
@@ -192,15 +206,15 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
     for (int r = 0; r < 4; ++r)
       if (r >= nact) mine_slots[t * 4 + r] = 0.0;
   solve_block<M, NW>(a, v, c0, nact, a.nz, carry, L0, fetch, emit);
-  __syncthreads();
-  double2* __restrict__ dst = (double2*)(a.dout + (long)s * a.strip);
+  wave_sync();
+  double2* __restrict__ dst = (double2*)(a.dout + (long)s * a.strip) + 2 * wrow0;
 #pragma unroll
   for (int u = 0; u < 2 * M; ++u) {
-    const int q = tid + u * NT;
-    const int j = q >> 1;
-    if (j < a.nz) {
-      const int kk = j / M, t = j - kk * M;
-      dst[q] = *(const double2*)&buf[kk * CH + t * 4 + (q & 1) * 2];
+    const int q = lane + u * 64;
+    const int jl = q >> 1;
+    if (wrow0 + jl < a.nz) {
+      const int kk = jl / M, t = jl - kk * M;
+      dst[q] = *(const double2*)&wbuf[kk * CH + t * 4 + (q & 1) * 2];
     }
   }
 }
@@ -226,18 +240,20 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
   const LineTab& tb = a.tabs[class_at(a.line_end, line0)];
   const int p0 = tid * M;
   LaneTab<M> L;
-  load_lanetab<M, NT>(L, tb.pos + tid, tb.chk + tid);
+  load_lanetab<M, NT>(L, tb.pos, tb.chk, tid);
   const unsigned long long live = chunk_live_mask(p0, M, a.nr, tb.skip_lo, tb.skip_hi);
   const int nstrips = (a.nr + 3) >> 2;
+  // each wave stages the 64 tiles of its own chunks through its own LDS region
+  const int lane = tid & 63, wst0 = (tid >> 6) * 64;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int q = tid + u * NT;  // tile q/8, piece q%8
-    const int st = q >> 3;
+    const int q = lane + u * 64;  // local tile q/8, piece q%8
+    const int st = wst0 + (q >> 3);
     double2 x = make_double2(0.0, 0.0);
     if (st < nstrips) x = *(const double2*)(a.din + (long)st * a.strip + (long)j0 * 4 + (q & 7) * 2);
     *(double2*)&buf[st * CH + (q & 7) * 2] = x;
   }
-  __syncthreads();
+  wave_sync();
   double* mine_slots = buf + tid * CH;
   if (lc < 0) {
     double v[4][M], o[4][M];
@@ -256,11 +272,11 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
       *(double2*)&mine_slots[r * 4] = make_double2(on ? o[r][0] : 0.0, on ? o[r][1] : 0.0);
       *(double2*)&mine_slots[r * 4 + 2] = make_double2(on ? o[r][2] : 0.0, on ? o[r][3] : 0.0);
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int q = tid + u * NT;
-      const int st = q >> 3;
+      const int q = lane + u * 64;
+      const int st = wst0 + (q >> 3);
       if (st < nstrips)
         *(double2*)(a.dout + (long)st * a.strip + (long)j0 * 4 + (q & 7) * 2) =
             *(const double2*)&buf[st * CH + (q & 7) * 2];
