@@ -567,21 +567,6 @@ adi_status launch_init_rhs(adi_problem p) {
   return ADI_OK;
 }
 
-// Cumulative class ends along one axis (dir 0: rows by band, 1: columns by
-// class): the class of index x is the number of q with x >= ends[q].
-void class_ends(const int* ranges, int dir, int ncls, int* ends) {
-  int e = 0;
-  for (int c = 0; c < 3; ++c) {
-    if (c < ncls) {
-      const int* rg = ranges + (dir * MAX_CLS + c) * 2;
-      if (rg[1] > rg[0]) e = rg[1];
-      ends[c] = c < ncls - 1 ? e : INT32_MAX;
-    } else {
-      ends[c] = INT32_MAX;
-    }
-  }
-}
-
 adi_status launch_strip_sweep(adi_problem p, int dir, const double* din, double* dout, double* xout) {
   const DirState& D = dir == 0 ? p->r : p->z;
   const DirState& X = dir == 0 ? p->z : p->r;
@@ -596,26 +581,9 @@ adi_status launch_strip_sweep(adi_problem p, int dir, const double* din, double*
   a.strip = p->strip;
   a.nr = p->P.nr;
   a.nz = p->P.nz;
-  a.nlines = D.nlines;
-  // lines of this direction: rows (bands) for r, columns (classes) for z
-  class_ends(p->ranges, dir == 0 ? 0 : 1, D.ncls, a.line_end);
-  class_ends(p->ranges, dir == 0 ? 1 : 0, X.ncls, a.pos_end);
-  a.nxcls = X.ncls;
-  a.nblocks = (D.nlines + 3) / 4;
-  a.nmix = 0;
-  if (dir == 0) {
-    // r sweep: row groups that straddle a band boundary, one row per workgroup
-    for (int q = 0; q < 3; ++q) {
-      const int e = a.line_end[q];
-      if (e <= 0 || e >= D.nlines || e % 4 == 0) continue;
-      bool seen = false;
-      for (int m = 0; m < a.nmix; ++m) seen = seen || a.mix[m] == e / 4;
-      if (!seen) a.mix[a.nmix++] = e / 4;
-    }
-  }
-  for (int m = a.nmix; m < 4; ++m) a.mix[m] = -1;
+  const int grid = strip_setup(a, p->ranges, dir, D.nlines, D.ncls, X.ncls);
   const StripVariant& V = kStrip[D.L.variant];
-  hipLaunchKernelGGL(V.fn, dim3(a.nblocks + 4 * a.nmix), dim3(64 * V.NW), 0, p->stream, a);
+  hipLaunchKernelGGL(V.fn, dim3(grid), dim3(64 * V.NW), 0, p->stream, a);
   ADI_CHECK_LAUNCH();
   return ADI_OK;
 }

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <stdint.h>
+
 #include "device.hpp"
 
 namespace adi {
@@ -46,6 +48,47 @@ struct StripArgs {
   int nmix;                 // r sweep: row groups whose rows are not all of one band ...
   int mix[4];               // ... solved one row per workgroup by nblocks + 4*m + row
 };
+
+// ---- host side: launch arguments shared by the library and its tests ----
+
+// Cumulative class ends along one axis (dir 0: rows by band, 1: columns by
+// class) from the class ranges of build_geometry: the class of index x is the
+// number of q with x >= ends[q].
+inline void strip_class_ends(const int* ranges, int dir, int ncls, int* ends) {
+  int e = 0;
+  for (int c = 0; c < 3; ++c) {
+    if (c < ncls) {
+      const int* rg = ranges + (dir * MAX_CLS + c) * 2;
+      if (rg[1] > rg[0]) e = rg[1];
+      ends[c] = c < ncls - 1 ? e : INT32_MAX;
+    } else {
+      ends[c] = INT32_MAX;
+    }
+  }
+}
+
+// Fill the class fields of a sweep's arguments and return its grid size.
+// dir 0 (r sweep): lines are rows (band classes), positions columns; row
+// groups straddling a band boundary get one workgroup per row.  dir 1 (z
+// sweep): lines are columns, positions rows; one workgroup per strip.
+inline int strip_setup(StripArgs& a, const int* ranges, int dir, int nlines, int ncls_lines, int ncls_pos) {
+  strip_class_ends(ranges, dir == 0 ? 0 : 1, ncls_lines, a.line_end);
+  strip_class_ends(ranges, dir == 0 ? 1 : 0, ncls_pos, a.pos_end);
+  a.nxcls = ncls_pos;
+  a.nlines = nlines;
+  a.nblocks = (nlines + 3) / 4;
+  a.nmix = 0;
+  if (dir == 0)
+    for (int q = 0; q < 3; ++q) {
+      const int e = a.line_end[q];
+      if (e <= 0 || e >= nlines || e % 4 == 0) continue;
+      bool seen = false;
+      for (int m = 0; m < a.nmix; ++m) seen = seen || a.mix[m] == e / 4;
+      if (!seen) a.mix[a.nmix++] = e / 4;
+    }
+  for (int m = a.nmix; m < 4; ++m) a.mix[m] = -1;
+  return a.nblocks + 4 * a.nmix;
+}
 
 // r sweep work of a workgroup: b < nblocks is row group b with all its rows
 // (lc = -1) unless the group is mixed (then nothing); b >= nblocks is row lc
