@@ -412,14 +412,151 @@ __device__ __forceinline__ unsigned long long chunk_live_mask(int p0, int M, int
   return below(m) & ~(below(skip_hi - p0) & ~below(skip_lo - p0));
 }
 
-// Solve one line group.  The group has LPW lane slots per wave, each slot
-// owning R consecutive lines; every line is spread over CPW = 64/LPW chunks
-// per wave and WPL waves, M cells per chunk.  A lane therefore holds an
-// R x M block: the same chunk of R lines, so each factor-table value it
-// loads serves R lines.  All sizes are compile-time, so every loop unrolls
-// without branches.  The reduced system is solved by recursive doubling on
-// affine maps (x_k = A + B x_{k-2^s}): (A, B) pairs are combined through
-// wave shuffles, with a carry through LDS when a line spans several waves.
+// ---- scans of affine maps over the chunks of a line slot ----
+//
+// A line slot is CPW consecutive lanes (CPW a power of two from 4 to 64),
+// lane ci of the slot holding chunk ci.  Forward: x_k = A_k + B_k x_{k-1},
+// lane ci ends with the composition over chunks 0..ci.  Backward: x_k = H_k +
+// E_k x_{k+1}, lane ci ends with the composition over chunks ci..CPW-1.
+// Steps inside rows of 16 lanes are DPP row shifts (lanes without a source
+// in the slot combine with the identity map); across rows the forward scan
+// uses DPP row broadcasts and the backward scan reads the row totals with
+// readlane.
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double old, double src) {
+  const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP broadcast across rows (row_bcast:15 / row_bcast:31), writing only the
+// rows in ROWS; other lanes keep `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast(double old, double src) {
+  const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CPW, int D, int R>
+__device__ __forceinline__ void fwd_step(double (&F)[R], double& B, int ci) {
+  if constexpr (D < CPW && D < 16) {
+    double Bo = dpp_row<0x110 + D>(1.0, B);
+    double Ao[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Ao[r] = dpp_row<0x110 + D>(0.0, F[r]);
+    if constexpr (CPW < 16) {  // slot starts inside a row
+      if (ci < D) {
+        Bo = 1.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) Ao[r] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] += B * Ao[r];
+    B *= Bo;
+  }
+}
+
+template <int CPW, int D, int R>
+__device__ __forceinline__ void bwd_step(double (&U)[R], double& E, int ci) {
+  if constexpr (D < CPW && D < 16) {
+    double Eo = dpp_row<0x100 + D>(1.0, E);
+    double Uo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Uo[r] = dpp_row<0x100 + D>(0.0, U[r]);
+    if constexpr (CPW < 16) {  // slot ends inside a row
+      if (ci + D >= CPW) {
+        Eo = 1.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) Uo[r] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) U[r] += E * Uo[r];
+    E *= Eo;
+  }
+}
+
+template <int CPW, int R>
+__device__ __forceinline__ void slot_scan_fwd(double (&F)[R], double& B) {
+  static_assert(CPW >= 4 && CPW <= 64 && (CPW & (CPW - 1)) == 0, "slot width");
+  const int ci = (threadIdx.x & 63) & (CPW - 1);
+  fwd_step<CPW, 1>(F, B, ci);
+  fwd_step<CPW, 2>(F, B, ci);
+  fwd_step<CPW, 4>(F, B, ci);
+  fwd_step<CPW, 8>(F, B, ci);
+  if constexpr (CPW >= 32) {
+    // rows 1 and 3 take the totals of rows 0 and 2 (lanes 15 and 47)
+    const double Bo = dpp_bcast<0x142, 0xa>(1.0, B);
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] += B * dpp_bcast<0x142, 0xa>(0.0, F[r]);
+    B *= Bo;
+  }
+  if constexpr (CPW == 64) {
+    // rows 2 and 3 take the total of rows 0..1 (lane 31)
+    const double Bo = dpp_bcast<0x143, 0xc>(1.0, B);
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] += B * dpp_bcast<0x143, 0xc>(0.0, F[r]);
+    B *= Bo;
+  }
+}
+
+template <int CPW, int R>
+__device__ __forceinline__ void slot_scan_bwd(double (&U)[R], double& E) {
+  static_assert(CPW >= 4 && CPW <= 64 && (CPW & (CPW - 1)) == 0, "slot width");
+  const int lane = threadIdx.x & 63;
+  const int ci = lane & (CPW - 1);
+  bwd_step<CPW, 1>(U, E, ci);
+  bwd_step<CPW, 2>(U, E, ci);
+  bwd_step<CPW, 4>(U, E, ci);
+  bwd_step<CPW, 8>(U, E, ci);
+  if constexpr (CPW >= 32) {
+    // rows compose the totals of the rows after them inside their slot
+    // (totals sit at the first lane of each row)
+    const int row = lane >> 4;
+    double cU[R], cE = 1.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) cU[r] = 0.0;
+#pragma unroll
+    for (int q = 3; q >= 1; --q) {
+      const double tE = read_lane(E, 16 * q);
+      double tU[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) tU[r] = read_lane(U[r], 16 * q);
+      // row `row` takes row q if q is after it within the same slot
+      const bool take = q > row && (q * 16) / CPW == (row * 16) / CPW;
+      if (take) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) cU[r] = tU[r] + tE * cU[r];
+        cE *= tE;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) U[r] += E * cU[r];
+    E *= cE;
+  }
+}
+
+// Solve one line group.  The group has LPW lane slots per wave (each slot
+// CPW = 64/LPW consecutive lanes) owning R consecutive lines; every line is
+// spread over CPW chunks per wave and WPL waves, M cells per chunk.  A lane
+// therefore holds an R x M block: the same chunk of R lines, so each
+// factor-table value it loads serves R lines.  All sizes are compile-time,
+// so every loop unrolls without branches.  The reduced system is solved by
+// recursive doubling on affine maps (x_k = A + B x_{k-2^s}) over the slot's
+// lanes with DPP row operations (slot_scan_fwd / slot_scan_bwd), with a
+// carry through LDS when a line spans several waves.
 // `lds` holds WPL*LPW*(R+1) doubles for this group; groups past the end
 // (valid = false) still take part in the barriers.
 // CONTIG: positions of a line are adjacent in memory (pos_stride == 1, r
@@ -432,10 +569,9 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
   constexpr int CPW = 64 / LPW;
   constexpr int G = CPW * WPL;
   constexpr int GM = G * M;
-  constexpr int LEV = __builtin_ctz(CPW);
   const int lane = threadIdx.x & 63;
-  const int li = lane % LPW;
-  const int ci = lane / LPW;
+  const int li = lane / CPW;  // line slot: CPW consecutive lanes
+  const int ci = lane % CPW;  // chunk within the wave's part of the line
   const int k = wv * CPW + ci;
 
   // class of the group (uniform across the group)
@@ -521,19 +657,7 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
     F[r] = (v[r][M - 1] - ae * v[r][M - 2]) * W1 - Q1 * g0w[r];
   }
   double B = Q1 * Q0;
-#pragma unroll
-  for (int lev = 0; lev < LEV; ++lev) {
-    const int d = 1 << lev;
-    const double Bo = __shfl_up(B, d * LPW, 64);
-    double Ao[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) Ao[r] = __shfl_up(F[r], d * LPW, 64);
-    if (ci >= d) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) F[r] += B * Ao[r];
-      B *= Bo;
-    }
-  }
+  slot_scan_fwd<CPW, R>(F, B);
   double Fin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Fin[r] = 0.0;
@@ -557,7 +681,7 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
   double Fprev[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    Fprev[r] = __shfl_up(F[r], LPW, 64);
+    Fprev[r] = __shfl_up(F[r], 1, 64);
     if (ci == 0) Fprev[r] = Fin[r];
   }
 
@@ -566,19 +690,7 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
 #pragma unroll
   for (int r = 0; r < R; ++r) U[r] = g0w[r] - Q0 * Fprev[r] - C0 * F[r];
   double E = C0 * C1;
-#pragma unroll
-  for (int lev = 0; lev < LEV; ++lev) {
-    const int d = 1 << lev;
-    const double Eo = __shfl_down(E, d * LPW, 64);
-    double Uo[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) Uo[r] = __shfl_down(U[r], d * LPW, 64);
-    if (ci + d < CPW) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) U[r] += E * Uo[r];
-      E *= Eo;
-    }
-  }
+  slot_scan_bwd<CPW, R>(U, E);
   double Uin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Uin[r] = 0.0;
@@ -604,7 +716,7 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
   double xm1[R], xp1[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    double un = __shfl_down(U[r], LPW, 64);
+    double un = __shfl_down(U[r], 1, 64);
     if (ci == CPW - 1) un = Uin[r];
     const double xs = U[r];
     const double xe = F[r] - C1 * un;
@@ -714,100 +826,6 @@ __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, 
   L.cprev = chk[C_CPREV * G + k];
 }
 
-// ---- wavefront scans of affine maps (x_k = A_k + B_k x_{k-1}) with DPP ----
-//
-// Within each row of 16 lanes the scan takes 4 steps of DPP row shifts
-// (each lane combines with the lane d below or above it; lanes without a
-// source combine with the identity map); the 4 row totals are then read
-// into scalar registers and composed, and each row applies the composition
-// of the rows before (forward) or after (backward) it.
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_row(double old, double src) {
-  const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
-  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// DPP broadcast across rows (row_bcast:15 / row_bcast:31), writing only the
-// rows in ROWS; other lanes keep `old`.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_bcast(double old, double src) {
-  const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
-  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROWS, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ __forceinline__ double read_lane(double v, int l) {
-  const long long x = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)x, l);
-  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Inclusive forward scan over the 64 lanes: on return lane k holds the
-// composition of the maps of lanes 0..k (F values per line, common factor B).
-template <int R>
-__device__ __forceinline__ void wave_scan_fwd(double (&F)[R], double& B) {
-  const int lane = threadIdx.x & 63;
-#define ADI_FWD_STEP(D)                                              \
-  {                                                                  \
-    const double Bo = dpp_row<0x110 + D>(1.0, B);                    \
-    _Pragma("unroll") for (int r = 0; r < R; ++r) F[r] += B * dpp_row<0x110 + D>(0.0, F[r]); \
-    B *= Bo;                                                         \
-  }
-  ADI_FWD_STEP(1) ADI_FWD_STEP(2) ADI_FWD_STEP(4) ADI_FWD_STEP(8)
-#undef ADI_FWD_STEP
-  // across rows: row_bcast:15 hands the last lane of rows 0 and 2 to rows 1
-  // and 3, then row_bcast:31 hands lane 31 to rows 2 and 3
-#define ADI_FWD_BCAST(CTRL, ROWS)                                                        \
-  {                                                                                     \
-    const double Bo = dpp_bcast<CTRL, ROWS>(1.0, B);                                    \
-    _Pragma("unroll") for (int r = 0; r < R; ++r) F[r] += B * dpp_bcast<CTRL, ROWS>(0.0, F[r]); \
-    B *= Bo;                                                                            \
-  }
-  ADI_FWD_BCAST(0x142, 0xa) ADI_FWD_BCAST(0x143, 0xc)
-#undef ADI_FWD_BCAST
-  (void)lane;
-}
-
-// Inclusive backward scan (x_k = H_k + E_k x_{k+1}): lane k ends with the
-// composition of the maps of lanes k..63.
-template <int R>
-__device__ __forceinline__ void wave_scan_bwd(double (&U)[R], double& E) {
-  const int lane = threadIdx.x & 63;
-#define ADI_BWD_STEP(D)                                              \
-  {                                                                  \
-    const double Eo = dpp_row<0x100 + D>(1.0, E);                    \
-    _Pragma("unroll") for (int r = 0; r < R; ++r) U[r] += E * dpp_row<0x100 + D>(0.0, U[r]); \
-    E *= Eo;                                                         \
-  }
-  ADI_BWD_STEP(1) ADI_BWD_STEP(2) ADI_BWD_STEP(4) ADI_BWD_STEP(8)
-#undef ADI_BWD_STEP
-  // row totals at lanes 48, 32, 16; suffix of the rows above each row
-  const int row = lane >> 4;
-  double cU[R], cE = 1.0;
-#pragma unroll
-  for (int r = 0; r < R; ++r) cU[r] = 0.0;
-#pragma unroll
-  for (int q = 3; q >= 1; --q) {
-    const double tE = read_lane(E, 16 * q);
-    double tU[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) tU[r] = read_lane(U[r], 16 * q);
-    if (row < q) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) cU[r] = tU[r] + tE * cU[r];
-      cE *= tE;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) U[r] += E * cU[r];
-  E *= cE;
-}
-
 // Solve a block of R lines that share one line class.  Lane k = 64*wave +
 // lane holds chunk k (M cells) of each of the R lines in v[R][M]; the NW
 // waves of the workgroup hold the G = 64*NW chunks of the lines.  Same
@@ -859,7 +877,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
     F[r] = (v[r][M - 1] - L.ae * v[r][M - 2]) * L.W1 - L.Q1 * g0w[r];
   }
   double B = L.Q1 * L.Q0;
-  wave_scan_fwd<R>(F, B);
+  slot_scan_fwd<64, R>(F, B);
   double Fin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Fin[r] = 0.0;
@@ -891,7 +909,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
 #pragma unroll
   for (int r = 0; r < R; ++r) U[r] = g0w[r] - L.Q0 * Fprev[r] - L.C0 * F[r];
   double E = L.C0 * L.C1;
-  wave_scan_bwd<R>(U, E);
+  slot_scan_bwd<64, R>(U, E);
   double Uin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Uin[r] = 0.0;

@@ -179,7 +179,7 @@ __device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], 
 template <int M, int NW>
 __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
   constexpr int NT = 64 * NW;
-  constexpr int CH = 4 * M;  // LDS doubles per chunk
+  constexpr int CH = 4 * M;  // LDS doubles per chunk (rows of 4, no padding)
   __shared__ __align__(16) double buf[NT * CH];
   __shared__ double carry[2 * NW * 5];
   const int s = xcd_block(blockIdx.x, gridDim.x);
@@ -198,14 +198,14 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
   const int lane = tid & 63, wrow0 = (tid >> 6) * 64 * M;
   double* wbuf = buf + (tid >> 6) * 64 * CH;
   const double2* __restrict__ src = (const double2*)(a.din + (long)s * a.strip) + 2 * wrow0;
+  // with 4*M doubles per chunk, local row jl sits at 4*jl in the wave's
+  // region, as in the strip: the copy is contiguous
 #pragma unroll
   for (int u = 0; u < 2 * M; ++u) {
     const int q = lane + u * 64;  // local row q/2, column pair q%2
-    const int jl = q >> 1;
     double2 x = make_double2(0.0, 0.0);
-    if (wrow0 + jl < a.nz) x = src[q];
-    const int kk = jl / M, t = jl - kk * M;
-    *(double2*)&wbuf[kk * CH + t * 4 + (q & 1) * 2] = x;
+    if (wrow0 + (q >> 1) < a.nz) x = src[q];
+    *(double2*)&wbuf[2 * q] = x;
   }
   wave_sync();
   double* mine_slots = buf + tid * CH;
@@ -254,11 +254,7 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
 #pragma unroll
   for (int u = 0; u < 2 * M; ++u) {
     const int q = lane + u * 64;
-    const int jl = q >> 1;
-    if (wrow0 + jl < a.nz) {
-      const int kk = jl / M, t = jl - kk * M;
-      dst[q] = *(const double2*)&wbuf[kk * CH + t * 4 + (q & 1) * 2];
-    }
+    if (wrow0 + (q >> 1) < a.nz) dst[q] = *(const double2*)&wbuf[2 * q];
   }
 }
 
