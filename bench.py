@@ -17,6 +17,8 @@ Prints one JSON line:
               the kernel runs on
   cpu_baseline  the CPU FP64 oracle timed on a bounded sample of the same
               workload on this host
+  single_layout  secondary figure: the 64x160 layout of Fig. 1, 1000 steps
+              (latency-bound; microseconds per step)
   batch       secondary figure: the ragged design batch (4096 seeded
               instances of 64x160 ... 192x480 cells, 2000 PR steps of 1e-3)
               in one persistent launch, autotuned; cell-updates/s and the
@@ -183,6 +185,35 @@ def summarize_counters(root):
     print(json.dumps(rec, indent=1))
 
 
+def single_layout_leg():
+    """The single layout of Fig. 1 at 64 x 160 (latency-bound: the field is
+    80 KB): 1000 backward-Euler LOD steps of 1e-3 in one timed call, in the
+    autotuned layout and shapes."""
+    import numpy as np
+    import torch
+
+    from paper_1912_03744_amd import autotune, native
+    from paper_1912_03744_amd import workloads as W
+    spec = W.single_layout()
+    p = native.Problem.from_spec(spec)
+    autotune.apply(p, spec.dt, spec.scheme)
+    p.set_graph_steps(100)
+    p.step(spec.dt, 100)
+    p.read_field()
+    p.set_field(None, spec.T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.step(spec.dt, spec.nsteps)
+    T = p.read_field()
+    wall = time.perf_counter() - t0
+    active = int(np.count_nonzero(~np.isnan(T)))
+    out = {"workload": "single layout of Fig. 1, 64x160, LOD backward Euler, dt=1e-3, 1000 steps",
+           "value": active * spec.nsteps / wall, "unit": "cell-updates/s", "us_per_step": wall * 1e6 / spec.nsteps,
+           "active_cells": active, "layout": p.layout(), "terminal_peak": float(np.nanmax(T[-1]))}
+    p.close()
+    return out
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--counter-workload":
         counter_workload(0)
@@ -281,6 +312,7 @@ def main():
         "energy_residual": rep["residual"],
     }
     p.close()
+    out["single_layout"] = single_layout_leg()
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_n, args.batch_steps, tune=not args.no_tune)
         print("bench: batch %.3f s, %.3e cell-updates/s" % (out["batch"]["seconds"], out["batch"]["value"]),

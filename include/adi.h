@@ -218,8 +218,10 @@ adi_status adi_batch_set_materials(adi_batch b, const double* k, const double* r
 adi_status adi_batch_set_initial(adi_batch b, const double* T0);
 
 /* Launch shape of the batch kernel (the autotuner uses it): lines per lane
- * (1 or 2), waves per workgroup (4 or 8), resident workgroups per compute
- * unit (1..8).  ADI_EUNSUPPORTED for shapes not compiled. */
+ * (1 or 2: right-hand sides by rows, line slots of 16 or 32 chunks; 4: right-
+ * hand sides in strips of 4 columns, one wave per block of 4 lines), waves
+ * per workgroup (4 or 8), resident workgroups per compute unit (1..8).
+ * ADI_EUNSUPPORTED for shapes not compiled. */
 adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t waves_per_block,
                                 int32_t blocks_per_cu);
 

@@ -139,9 +139,10 @@ def apply(problem, dt, scheme, retune=False, verbose=False, log=None):
     return entry
 
 
-# compiled batch kernels: (lines per lane, waves per workgroup); resident
-# workgroups per compute unit is a launch parameter
-BATCH_KERNELS = ((1, 4), (2, 4), (1, 8), (2, 8))
+# compiled batch kernels: (lines per lane, waves per workgroup), 4 lines
+# per lane being the strip-layout kernel; resident workgroups per compute
+# unit is a launch parameter
+BATCH_KERNELS = ((1, 4), (2, 4), (1, 8), (2, 8), (4, 4), (4, 8))
 BATCH_BLOCKS_PER_CU = (1, 2, 4)
 
 

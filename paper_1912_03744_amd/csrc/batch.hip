@@ -18,55 +18,9 @@
 
 #include "common.hpp"
 #include "device.hpp"
+#include "batch.hpp"
 
 namespace adi {
-
-// Compiled line shapes of the batch kernel (one wave per line group):
-// r lines use 4 lines x 16 chunks per wave, z lines 2 lines x 32 chunks.
-constexpr int kBR_LPW = 4, kBR_G = 16;
-constexpr int kBZ_LPW = 2, kBZ_G = 32;
-constexpr int kBR_M[4] = {4, 6, 8, 12};   // r lines up to 64, 96, 128, 192 cells
-constexpr int kBZ_M[4] = {5, 8, 10, 15};  // z lines up to 160, 256, 320, 480 cells
-constexpr int kMaxNr = 192, kMaxNz = 480;
-
-struct BatchInst {
-  Params P;
-  long toff;   // offset of the instance's field in the arena (doubles)
-  int rs, zs;  // shape index of its r and z lines
-  double T0;   // uniform initial temperature
-};
-
-// Byte offsets inside one workgroup's scratch area.
-struct BatchLayout {
-  long dA, dB, geo, kap, bet, ranges, rtabs, rpos, rchk, reng, rxc, ztabs, zpos, zchk, zeng, zxc, work;
-  long stride;
-};
-
-struct BatchArgs {
-  const BatchInst* inst;
-  const int* order;
-  int ninst;
-  int* queue;
-  double* T;
-  double* prof;
-  int nsnap, npts, snap_every;
-  int nsteps;
-  char* scratch;
-  BatchLayout lay;
-};
-
-__device__ __forceinline__ void skip_range(int dir, int cls, const int* ranges, int n, int* lo, int* hi) {
-  // masked cells of an r line in band 1: columns of classes 1..3, i.e. from
-  // the end of column class 0; of a z line of class >= 1: rows of band 1
-  *lo = *hi = n;
-  if (dir == 0 && cls == 1) {
-    const int i0 = ranges[(1 * MAX_CLS + 0) * 2 + 1];
-    if (i0 < n) { *lo = i0; *hi = n; }
-  } else if (dir == 1 && cls >= 1) {
-    const int a = ranges[(0 * MAX_CLS + 1) * 2], b = ranges[(0 * MAX_CLS + 1) * 2 + 1];
-    if (b > a) { *lo = a; *hi = b; }
-  }
-}
 
 __device__ void fill_sweep_args(SweepArgs& s, int dir, const Params& P, const Geom& g, const int* ranges,
                                 const LineTab* tabs, const double* xc_other, int lines_per_group) {
@@ -246,8 +200,11 @@ struct BatchVariant {
   int R, NW;
   BatchFn fn;
 };
+// R = 1, 2: rows-layout line solver; R = 4: the strip-layout kernel
+// (4 lines per lane, one wave per block of lines).
 static const BatchVariant kBatchVariants[] = {
     {1, 4, k_batch<1, 4>}, {2, 4, k_batch<2, 4>}, {1, 8, k_batch<1, 8>}, {2, 8, k_batch<2, 8>},
+    {4, 4, k_batch_s<4>},  {4, 8, k_batch_s<8>},
 };
 static const int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 
@@ -257,7 +214,7 @@ static int shape_index(const int* cover_m, int G, int n) {
   return -1;
 }
 
-static BatchLayout make_layout(long maxcells) {
+static BatchLayout make_layout(long maxcells, long maxstrip) {
   BatchLayout L{};
   long off = 0;
   auto put = [&](long bytes) {
@@ -265,24 +222,28 @@ static BatchLayout make_layout(long maxcells) {
     off += (bytes + 255) & ~255L;
     return o;
   };
-  const long rGM = (long)kBR_G * kBR_M[3], zGM = (long)kBZ_G * kBZ_M[3];
-  L.dA = put(8 * maxcells);
-  L.dB = put(8 * maxcells);
+  // tables sized for both kernel families (rows layout, strip layout)
+  const long rGM = std::max((long)kBR_G * kBR_M[3], (long)kBS_G * kBSR_M);
+  const long zGM = std::max((long)kBZ_G * kBZ_M[3], (long)kBS_G * kBSZ_M[3]);
+  const long rG = std::max(kBR_G, kBS_G), zG = std::max(kBZ_G, kBS_G);
+  L.dA = put(8 * std::max(maxcells, maxstrip));
+  L.dB = put(8 * std::max(maxcells, maxstrip));
   L.geo = put(8 * (3 * (kMaxNr + 1) + 3 * (kMaxNz + 1)));
   L.kap = put(kMaxNr);
   L.bet = put(kMaxNz);
   L.ranges = put(4 * 17);
   L.rtabs = put(sizeof(LineTab) * 3);
   L.rpos = put(8 * 3 * P_NFIELDS * rGM);
-  L.rchk = put(8 * 3 * C_NFIELDS * kBR_G);
+  L.rchk = put(8 * 3 * C_NFIELDS * rG);
   L.reng = put(8 * 3 * 2 * kMaxNr);
   L.rxc = put(8 * 3 * kMaxNr);
   L.ztabs = put(sizeof(LineTab) * 4);
   L.zpos = put(8 * 4 * P_NFIELDS * zGM);
-  L.zchk = put(8 * 4 * C_NFIELDS * kBZ_G);
+  L.zchk = put(8 * 4 * C_NFIELDS * zG);
   L.zeng = put(8 * 4 * 2 * kMaxNz);
   L.zxc = put(8 * 4 * kMaxNz);
-  L.work = put(8 * std::max(assemble_work(kBR_G, kBR_M[3]), assemble_work(kBZ_G, kBZ_M[3])));
+  L.work = put(8 * std::max(std::max(assemble_work(kBR_G, kBR_M[3]), assemble_work(kBZ_G, kBZ_M[3])),
+                            std::max(assemble_work(kBS_G, kBSR_M), assemble_work(kBS_G, kBSZ_M[3]))));
   L.stride = off;
   return L;
 }
@@ -304,6 +265,7 @@ struct adi_batch_s {
   double* T = nullptr;
   long total_cells = 0, maxcells = 0;  // arena size (aligned), largest instance
   long cells = 0, active = 0;           // cells, cells inside the domain
+  long maxstrip = 0;                    // largest right-hand side in the strip layout (doubles)
   double* prof = nullptr;
   long prof_cap = 0;  // doubles
   int nsnap = 0, npts = 64;
@@ -386,6 +348,8 @@ adi_status adi_create_batch(int32_t n, const adi_geometry* geoms, const adi_bc* 
     for (int c = 0; c < 4; ++c) { P.h[c] = bc.h[c]; P.tinf[c] = bc.t_inf[c]; }
     I.rs = shape_index(kBR_M, kBR_G, g.nr);
     I.zs = shape_index(kBZ_M, kBZ_G, g.nz);
+    I.zss = batch_strip_zshape(g.nz);
+    b->maxstrip = std::max(b->maxstrip, batch_strip_doubles(g.nr, g.nz));
     I.toff = off;
     off += ((long)g.nr * g.nz + 31) & ~31L;  // 256-byte aligned fields (16-byte vector stores)
     b->maxcells = std::max(b->maxcells, (long)g.nr * g.nz);
@@ -401,7 +365,7 @@ adi_status adi_create_batch(int32_t n, const adi_geometry* geoms, const adi_bc* 
     b->active += (long)g.nr * g.nz - ncol * nrow;
   }
   b->total_cells = off;
-  b->lay = make_layout(b->maxcells);
+  b->lay = make_layout(b->maxcells, b->maxstrip);
   hipError_t e = hipGetDevice(&b->device);
   if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
   b->stream = (hipStream_t)hip_stream;

@@ -54,7 +54,7 @@ struct StripArgs {
 // Cumulative class ends along one axis (dir 0: rows by band, 1: columns by
 // class) from the class ranges of build_geometry: the class of index x is the
 // number of q with x >= ends[q].
-inline void strip_class_ends(const int* ranges, int dir, int ncls, int* ends) {
+__host__ __device__ inline void strip_class_ends(const int* ranges, int dir, int ncls, int* ends) {
   int e = 0;
   for (int c = 0; c < 3; ++c) {
     if (c < ncls) {
@@ -148,9 +148,8 @@ __device__ __forceinline__ void add_crossing(const StripArgs& a, double (*o)[M],
 // refetching the block's right-hand side with `fetch`.  L: the tables of the
 // first class, already loaded; later passes reload it.
 template <int M, int NW, class Fetch, class Emit>
-__device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], int line0, int nact, int n,
+__device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], int line0, int nact, int n, int tid,
                                             double* carry, LaneTab<M>& L, Fetch fetch, Emit emit) {
-  const int tid = threadIdx.x;
   const int p0 = tid * M;
   const int c_lo = class_at(a.line_end, line0), c_hi = class_at(a.line_end, line0 + nact - 1);
   auto lines_of = [&](int c) {
@@ -172,18 +171,15 @@ __device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], 
   }
 }
 
-// z sweep: workgroup per strip (4 adjacent columns), lane k holds rows
-// [kM, kM+M) of the strip's columns.  Each lane reads and writes only its
-// own chunk's LDS slots between the staging copies, which each wave does for
-// its own chunks.
+// Each lane reads and writes only its own chunk's LDS slots between the
+// staging copies, which each wave does for its own chunks.
+// The z-sweep work on strip s by lanes tid = 0 .. 64*NW-1 (a workgroup, or
+// one wave when NW = 1), staging through buf (64*NW*4*M doubles) and
+// carrying through `carry` (2*NW*5 doubles).
 template <int M, int NW>
-__global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
+__device__ __forceinline__ void strip_z_body(const StripArgs& a, int s, int tid, double* buf, double* carry) {
   constexpr int NT = 64 * NW;
   constexpr int CH = 4 * M;  // LDS doubles per chunk (rows of 4, no padding)
-  __shared__ __align__(16) double buf[NT * CH];
-  __shared__ double carry[2 * NW * 5];
-  const int s = xcd_block(blockIdx.x, gridDim.x);
-  const int tid = threadIdx.x;
   const int c0 = 4 * s;
   const int nact = min(4, a.nr - c0);
   const int p0 = tid * M;
@@ -248,13 +244,97 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       if (r >= nact) mine_slots[t * 4 + r] = 0.0;
-  solve_block<M, NW>(a, v, c0, nact, a.nz, carry, L0, fetch, emit);
+  solve_block<M, NW>(a, v, c0, nact, a.nz, tid, carry, L0, fetch, emit);
   wave_sync();
   double2* __restrict__ dst = (double2*)(a.dout + (long)s * a.strip) + 2 * wrow0;
 #pragma unroll
   for (int u = 0; u < 2 * M; ++u) {
     const int q = lane + u * 64;
     if (wrow0 + (q >> 1) < a.nz) dst[q] = *(const double2*)&wbuf[2 * q];
+  }
+}
+
+// z sweep: workgroup per strip (4 adjacent columns), lane k holds rows
+// [kM, kM+M) of the strip's columns.
+template <int M, int NW>
+__global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
+  __shared__ __align__(16) double buf[64 * NW * 4 * M];
+  __shared__ double carry[2 * NW * 5];
+  strip_z_body<M, NW>(a, xcd_block(blockIdx.x, gridDim.x), threadIdx.x, buf, carry);
+}
+
+// The r-sweep work on row group J by lanes tid = 0 .. 64*NW-1, solving the
+// rows of each band present in one pass per band (used by the batch, where
+// a workgroup holds no extra rows to hand out), staging through buf
+// (64*NW*18 doubles).
+template <int NW>
+__device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid, double* buf, double* carry) {
+  constexpr int M = 4;
+  constexpr int NT = 64 * NW;
+  constexpr int CH = 18;  // a 16-double tile + 2 pad
+  const int j0 = 4 * J;
+  const int nact = min(4, a.nz - j0);
+  const int p0 = tid * M;
+  LaneTab<M> L0;
+  {
+    const LineTab& tb = a.tabs[class_at(a.line_end, j0)];
+    load_lanetab<M, NT>(L0, tb.pos, tb.chk, tid);
+  }
+  const int nstrips = (a.nr + 3) >> 2;
+  const int lane = tid & 63, wst0 = (tid >> 6) * 64;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = lane + u * 64;  // local tile q/8, piece q%8
+    const int st = wst0 + (q >> 3);
+    double2 x = make_double2(0.0, 0.0);
+    if (st < nstrips) x = *(const double2*)(a.din + (long)st * a.strip + (long)j0 * 4 + (q & 7) * 2);
+    *(double2*)&buf[st * CH + (q & 7) * 2] = x;
+  }
+  wave_sync();
+  double* mine_slots = buf + tid * CH;
+  auto fetch = [&](double (*v)[M]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double2 lo = *(const double2*)&mine_slots[r * 4];
+      const double2 hi = *(const double2*)&mine_slots[r * 4 + 2];
+      v[r][0] = lo.x; v[r][1] = lo.y; v[r][2] = hi.x; v[r][3] = hi.y;
+    }
+  };
+  auto emit = [&](double (*v)[M], double (*o)[M], unsigned mask) {
+    if (a.xc) add_crossing<M>(a, o, j0, mask, a.nr, p0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if ((mask >> r) & 1u) {
+        *(double2*)&mine_slots[r * 4] = make_double2(o[r][0], o[r][1]);
+        *(double2*)&mine_slots[r * 4 + 2] = make_double2(o[r][2], o[r][3]);
+      }
+    if (a.xout) {
+      const int i0 = 4 * tid;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if ((mask >> r) & 1u)
+#pragma unroll
+          for (int t = 0; t < M; ++t)
+            if (i0 + t < a.nr) a.xout[(long)(j0 + r) * a.nr + i0 + t] = v[r][t];
+    }
+  };
+  double v[4][M];
+  fetch(v);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r >= nact) {
+      *(double2*)&mine_slots[r * 4] = make_double2(0.0, 0.0);
+      *(double2*)&mine_slots[r * 4 + 2] = make_double2(0.0, 0.0);
+    }
+  solve_block<M, NW>(a, v, j0, nact, a.nr, tid, carry, L0, fetch, emit);
+  wave_sync();
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = lane + u * 64;
+    const int st = wst0 + (q >> 3);
+    if (st < nstrips)
+      *(double2*)(a.dout + (long)st * a.strip + (long)j0 * 4 + (q & 7) * 2) =
+          *(const double2*)&buf[st * CH + (q & 7) * 2];
   }
 }
 
