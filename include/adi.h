@@ -154,10 +154,12 @@ adi_status adi_read_profile(adi_problem p, int32_t which, int32_t npts, double* 
 /* Energy report of the current field.  Synchronises. */
 adi_status adi_energy(adi_problem p, adi_energy_report* out);
 
-/* Kernel timing for the roofline report: launches the r sweep nlaunch times,
- * then the z sweep nlaunch times, each bracketed by HIP events on the
- * problem's stream, and returns the mean duration per launch in ms.  The
- * field is left unchanged.  Synchronises. */
+/* Kernel timing for the roofline report: nlaunch half-step pairs (r sweep,
+ * then z sweep, each reading what the other has just written, as in a time
+ * step) on the problem's side buffers and stream, every launch carrying HIP
+ * start and end events of its own dispatch; returns the mean duration per
+ * launch of each direction in ms.  The field and the carried right-hand side are left
+ * unchanged.  Synchronises. */
 adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_r, float* ms_z);
 
 /* Launch shape of the line solves (advanced; the autotuner uses it).

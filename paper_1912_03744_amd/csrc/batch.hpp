@@ -85,7 +85,7 @@ __host__ __device__ inline long batch_strip_doubles(int nr, int nz) {
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_batch_s(BatchArgs a) {
   __shared__ __align__(16) double lbuf[NW][64 * 4 * 8];  // per wave: a z strip or 64 r tiles
-  __shared__ double lcarry[NW][2 * 5];                   // unused: one wave per line
+  __shared__ double lcarry[NW][strip_carry(1)];          // unused: one wave per line
   __shared__ LineTab s_tabs[2][MAX_CLS];
   __shared__ StripArgs s_args[2];  // r sweep, z sweep
   __shared__ int s_next;
@@ -174,6 +174,7 @@ __global__ void __launch_bounds__(64 * NW) k_batch_s(BatchArgs a) {
       az.nxcls = 3;
       ar.nblocks = az.nblocks = 0;
       ar.nmix = az.nmix = 0;
+      ar.theta = az.theta = P.theta;
       ar.din = dA; ar.dout = dB; ar.xout = nullptr;
       az.din = dB; az.dout = dA; az.xout = nullptr;
     }

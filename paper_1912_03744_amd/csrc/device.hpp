@@ -81,6 +81,8 @@ enum PosField {
   P_OL,      //   lower neighbour
   P_OU,      //   upper neighbour
   P_OC,      //   constant
+  P_OK,      // (1 + theta) rho c / tau_a: with the solve's own right-hand
+             // side d, od x + ol x[-1] + ou x[+1] + oc = P_OK x - theta d + oc
   P_NFIELDS
 };
 
@@ -213,6 +215,7 @@ __device__ __forceinline__ double series2(double da, double ka, double db, doubl
 struct RowCoef {
   double a, b, c;          // matrix: a x[p-1] + b x[p] + c x[p+1]
   double od, ol, ou, oc;   // output operator
+  double ok;               // (1 + theta) C: diagonal of the output operator written against d
   double bw, bt;           // boundary flow weight and its T_inf part
   double bconst;           // boundary constant b of this direction's operator
 };
@@ -220,7 +223,7 @@ struct RowCoef {
 // dir 0: r line in band `cls` at position i; dir 1: z line of column class
 // `cls` at position j.  Balance form of eq. 10 (r) or eq. 11 (z).
 __device__ RowCoef row_coef(const Params& P, const Geom& g, int dir, int cls, int p) {
-  RowCoef R = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  RowCoef R = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int n = dir == 0 ? P.nr : P.nz;
   if (p >= n) return R;  // padding: identity row
   auto reg = [&](int q) {
@@ -285,6 +288,8 @@ __device__ RowCoef row_coef(const Params& P, const Geom& g, int dir, int cls, in
   // r sweep output: theta (b_r + Q) (+ b_z from the crossing table);
   // z sweep output: theta b_z + Q (+ b_r from the crossing table).
   R.oc = dir == 0 ? P.theta * (bconst + P.q[m]) : P.theta * bconst + P.q[m];
+  // od = (1 + theta) C - theta b, ol = -theta a, ou = -theta c
+  R.ok = (1.0 + P.theta) * C;
   R.bw = bw;
   R.bt = bt;
   R.bconst = bconst;
@@ -321,6 +326,7 @@ __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls,
     pos[P_OL * GM + ix] = R.ol;
     pos[P_OU * GM + ix] = R.ou;
     pos[P_OC * GM + ix] = R.oc;
+    pos[P_OK * GM + ix] = R.ok;
     if (p < n) {
       eng[p] = R.bw;
       eng[n + p] = R.bt;
@@ -431,6 +437,16 @@ __device__ __forceinline__ double dpp_row(double old, double src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The same row shift with 0 in lanes without a source (DPP bound control),
+// so no identity value has to be placed in the destination first.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row0(double src) {
+  const long long v = __double_as_longlong(src);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // DPP broadcast across rows (row_bcast:15 / row_bcast:31), writing only the
 // rows in ROWS; other lanes keep `old`.
 template <int CTRL, int ROWS>
@@ -448,89 +464,102 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int CPW, int D, int R>
-__device__ __forceinline__ void fwd_step(double (&F)[R], double& B, int ci) {
+// The R values of a lane belong to R lines; lines r < NA compose with the
+// multiplier BA, the others with BB (lines of two classes in one block).
+template <int CPW, int D, int R, int NA>
+__device__ __forceinline__ void fwd_step(double (&F)[R], double& BA, double& BB, int ci) {
   if constexpr (D < CPW && D < 16) {
-    double Bo = dpp_row<0x110 + D>(1.0, B);
+    double BoA = dpp_row<0x110 + D>(1.0, BA);
+    double BoB = NA < R ? dpp_row<0x110 + D>(1.0, BB) : 1.0;
     double Ao[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) Ao[r] = dpp_row<0x110 + D>(0.0, F[r]);
+    for (int r = 0; r < R; ++r) Ao[r] = dpp_row0<0x110 + D>(F[r]);
     if constexpr (CPW < 16) {  // slot starts inside a row
       if (ci < D) {
-        Bo = 1.0;
+        BoA = BoB = 1.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) Ao[r] = 0.0;
       }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) F[r] += B * Ao[r];
-    B *= Bo;
+    for (int r = 0; r < R; ++r) F[r] += (r < NA ? BA : BB) * Ao[r];
+    BA *= BoA;
+    if constexpr (NA < R) BB *= BoB;
   }
 }
 
-template <int CPW, int D, int R>
-__device__ __forceinline__ void bwd_step(double (&U)[R], double& E, int ci) {
+template <int CPW, int D, int R, int NA>
+__device__ __forceinline__ void bwd_step(double (&U)[R], double& EA, double& EB, int ci) {
   if constexpr (D < CPW && D < 16) {
-    double Eo = dpp_row<0x100 + D>(1.0, E);
+    double EoA = dpp_row<0x100 + D>(1.0, EA);
+    double EoB = NA < R ? dpp_row<0x100 + D>(1.0, EB) : 1.0;
     double Uo[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) Uo[r] = dpp_row<0x100 + D>(0.0, U[r]);
+    for (int r = 0; r < R; ++r) Uo[r] = dpp_row0<0x100 + D>(U[r]);
     if constexpr (CPW < 16) {  // slot ends inside a row
       if (ci + D >= CPW) {
-        Eo = 1.0;
+        EoA = EoB = 1.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) Uo[r] = 0.0;
       }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) U[r] += E * Uo[r];
-    E *= Eo;
+    for (int r = 0; r < R; ++r) U[r] += (r < NA ? EA : EB) * Uo[r];
+    EA *= EoA;
+    if constexpr (NA < R) EB *= EoB;
   }
 }
 
-template <int CPW, int R>
-__device__ __forceinline__ void slot_scan_fwd(double (&F)[R], double& B) {
+template <int CPW, int R, int NA = R>
+__device__ __forceinline__ void slot_scan_fwd(double (&F)[R], double& BA, double& BB) {
   static_assert(CPW >= 4 && CPW <= 64 && (CPW & (CPW - 1)) == 0, "slot width");
+  static_assert(NA >= 1 && NA <= R, "split");
   const int ci = (threadIdx.x & 63) & (CPW - 1);
-  fwd_step<CPW, 1>(F, B, ci);
-  fwd_step<CPW, 2>(F, B, ci);
-  fwd_step<CPW, 4>(F, B, ci);
-  fwd_step<CPW, 8>(F, B, ci);
+  fwd_step<CPW, 1, R, NA>(F, BA, BB, ci);
+  fwd_step<CPW, 2, R, NA>(F, BA, BB, ci);
+  fwd_step<CPW, 4, R, NA>(F, BA, BB, ci);
+  fwd_step<CPW, 8, R, NA>(F, BA, BB, ci);
   if constexpr (CPW >= 32) {
     // rows 1 and 3 take the totals of rows 0 and 2 (lanes 15 and 47)
-    const double Bo = dpp_bcast<0x142, 0xa>(1.0, B);
+    const double BoA = dpp_bcast<0x142, 0xa>(1.0, BA);
+    const double BoB = NA < R ? dpp_bcast<0x142, 0xa>(1.0, BB) : 1.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) F[r] += B * dpp_bcast<0x142, 0xa>(0.0, F[r]);
-    B *= Bo;
+    for (int r = 0; r < R; ++r) F[r] += (r < NA ? BA : BB) * dpp_bcast<0x142, 0xa>(0.0, F[r]);
+    BA *= BoA;
+    if constexpr (NA < R) BB *= BoB;
   }
   if constexpr (CPW == 64) {
     // rows 2 and 3 take the total of rows 0..1 (lane 31)
-    const double Bo = dpp_bcast<0x143, 0xc>(1.0, B);
+    const double BoA = dpp_bcast<0x143, 0xc>(1.0, BA);
+    const double BoB = NA < R ? dpp_bcast<0x143, 0xc>(1.0, BB) : 1.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) F[r] += B * dpp_bcast<0x143, 0xc>(0.0, F[r]);
-    B *= Bo;
+    for (int r = 0; r < R; ++r) F[r] += (r < NA ? BA : BB) * dpp_bcast<0x143, 0xc>(0.0, F[r]);
+    BA *= BoA;
+    if constexpr (NA < R) BB *= BoB;
   }
 }
 
-template <int CPW, int R>
-__device__ __forceinline__ void slot_scan_bwd(double (&U)[R], double& E) {
+template <int CPW, int R, int NA = R>
+__device__ __forceinline__ void slot_scan_bwd(double (&U)[R], double& EA, double& EB) {
   static_assert(CPW >= 4 && CPW <= 64 && (CPW & (CPW - 1)) == 0, "slot width");
+  static_assert(NA >= 1 && NA <= R, "split");
   const int lane = threadIdx.x & 63;
   const int ci = lane & (CPW - 1);
-  bwd_step<CPW, 1>(U, E, ci);
-  bwd_step<CPW, 2>(U, E, ci);
-  bwd_step<CPW, 4>(U, E, ci);
-  bwd_step<CPW, 8>(U, E, ci);
+  bwd_step<CPW, 1, R, NA>(U, EA, EB, ci);
+  bwd_step<CPW, 2, R, NA>(U, EA, EB, ci);
+  bwd_step<CPW, 4, R, NA>(U, EA, EB, ci);
+  bwd_step<CPW, 8, R, NA>(U, EA, EB, ci);
   if constexpr (CPW >= 32) {
     // rows compose the totals of the rows after them inside their slot
     // (totals sit at the first lane of each row)
     const int row = lane >> 4;
-    double cU[R], cE = 1.0;
+    double cU[R], cEA = 1.0, cEB = 1.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) cU[r] = 0.0;
 #pragma unroll
     for (int q = 3; q >= 1; --q) {
-      const double tE = read_lane(E, 16 * q);
+      const double tEA = read_lane(EA, 16 * q);
+      const double tEB = NA < R ? read_lane(EB, 16 * q) : 1.0;
       double tU[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) tU[r] = read_lane(U[r], 16 * q);
@@ -538,14 +567,26 @@ __device__ __forceinline__ void slot_scan_bwd(double (&U)[R], double& E) {
       const bool take = q > row && (q * 16) / CPW == (row * 16) / CPW;
       if (take) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) cU[r] = tU[r] + tE * cU[r];
-        cE *= tE;
+        for (int r = 0; r < R; ++r) cU[r] = tU[r] + (r < NA ? tEA : tEB) * cU[r];
+        cEA *= tEA;
+        if constexpr (NA < R) cEB *= tEB;
       }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) U[r] += E * cU[r];
-    E *= cE;
+    for (int r = 0; r < R; ++r) U[r] += (r < NA ? EA : EB) * cU[r];
+    EA *= cEA;
+    if constexpr (NA < R) EB *= cEB;
   }
+}
+
+// One multiplier for all R lines.
+template <int CPW, int R>
+__device__ __forceinline__ void slot_scan_fwd(double (&F)[R], double& B) {
+  slot_scan_fwd<CPW, R, R>(F, B, B);
+}
+template <int CPW, int R>
+__device__ __forceinline__ void slot_scan_bwd(double (&U)[R], double& E) {
+  slot_scan_bwd<CPW, R, R>(U, E, E);
 }
 
 // Solve one line group.  The group has LPW lane slots per wave (each slot
@@ -789,13 +830,13 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
 typedef const __attribute__((address_space(1))) double* gptr;
 
 // The factor-table values one lane needs for its chunk k of a line class:
-// interior factors (rows 1..M-2), output operator (all rows), reduced-system
-// factors of the chunk.  Loaded once, ahead of the data.
+// interior factors (rows 1..M-2), output scale and constant (all rows),
+// reduced-system factors of the chunk.  Loaded once, ahead of the data.
 template <int M>
 struct LaneTab {
   double w[M], qa[M], cp[M], sp[M], sr[M];
-  double od[M], ol[M], ou[M], oc[M];
-  double cs, ae, W0, Q0, C0, W1, Q1, C1, cprev;
+  double ok[M], oc[M];
+  double cs, ae, W0, Q0, C0, W1, Q1, C1;
 };
 
 // pos/chk: the class tables (uniform across the workgroup), k: the lane's
@@ -815,38 +856,34 @@ __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, 
   }
 #pragma unroll
   for (int t = 0; t < M; ++t) {
-    L.od[t] = pos[P_OD * GM + t * G + k];
-    L.ol[t] = pos[P_OL * GM + t * G + k];
-    L.ou[t] = pos[P_OU * GM + t * G + k];
+    L.ok[t] = pos[P_OK * GM + t * G + k];
     L.oc[t] = pos[P_OC * GM + t * G + k];
   }
   L.cs = chk[C_CS * G + k]; L.ae = chk[C_AE * G + k];
   L.W0 = chk[C_W0 * G + k]; L.Q0 = chk[C_Q0 * G + k]; L.C0 = chk[C_C0 * G + k];
   L.W1 = chk[C_W1 * G + k]; L.Q1 = chk[C_Q1 * G + k]; L.C1 = chk[C_C1 * G + k];
-  L.cprev = chk[C_CPREV * G + k];
 }
 
-// Solve a block of R lines that share one line class.  Lane k = 64*wave +
-// lane holds chunk k (M cells) of each of the R lines in v[R][M]; the NW
-// waves of the workgroup hold the G = 64*NW chunks of the lines.  Same
-// partition method as solve_group (interior elimination with the class's
-// precomputed factors, reduced system by recursive doubling over the chunks,
-// back substitution), with data and factors already in registers.  On
-// return v holds the solution and o the next half step's right-hand side
-// without the crossing constants (0 outside the domain, given a right-hand
-// side that is 0 there).  `lds` holds 2*NW*(R+1) doubles.  Every lane of the workgroup must call this (it
-// contains barriers when NW > 1).
-template <int M, int NW, int R>
-__device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], const LaneTab<M>& L,
-                                            unsigned long long live, double* lds) {
+// Solve a block of R lines in place.  Lane k = 64*wave + lane holds chunk
+// k (M cells) of each of the R lines in v[R][M]; the NW waves of the
+// workgroup hold the G = 64*NW chunks of the lines.  Lines r < NA have the
+// factors LA, the others LB (a block whose lines span two classes; NA = R:
+// one class, LB unused).  Same partition method as solve_group (interior
+// elimination with the class's precomputed factors, reduced system by
+// recursive doubling over the chunks, back substitution), with data and
+// factors already in registers.  Cells outside the domain and past the
+// line's end are identity rows carrying exactly 0 in every right-hand side,
+// so they solve to 0 without masking.  `lds` holds 2*NW*(R+2) doubles.
+// Every lane of the workgroup must call this (it contains barriers when
+// NW > 1).
+template <int M, int NW, int R, int NA>
+__device__ __forceinline__ void solve_lanes(double (*v)[M], const LaneTab<M>& LA, const LaneTab<M>& LB,
+                                            double* lds) {
   static_assert(M >= 3, "chunks need an interior row");
+  static_assert(NA >= 1 && NA <= R, "split");
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-
-  // Cells outside the domain and past the line's end are identity rows with
-  // a zero output operator and carry exactly 0 in every right-hand side, so
-  // they solve to 0 and produce 0 without masking.
-  (void)live;
+#define ADI_TAB(r) ((r) < NA ? LA : LB)
 
   // interior forward elimination and back substitution (rows 1..M-2)
   double run[R];
@@ -856,7 +893,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
   for (int t = 1; t <= M - 2; ++t)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      run[r] = v[r][t] * L.w[t] - L.qa[t] * run[r];
+      run[r] = v[r][t] * ADI_TAB(r).w[t] - ADI_TAB(r).qa[t] * run[r];
       v[r][t] = run[r];
     }
 #pragma unroll
@@ -865,7 +902,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
   for (int t = M - 2; t >= 1; --t)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      run[r] = v[r][t] - L.cp[t] * run[r];
+      run[r] = v[r][t] - ADI_TAB(r).cp[t] * run[r];
       v[r][t] = run[r];
     }
 
@@ -873,11 +910,12 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
   double g0w[R], F[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    const LaneTab<M>& L = ADI_TAB(r);
     g0w[r] = (v[r][0] - L.cs * v[r][1]) * L.W0;
     F[r] = (v[r][M - 1] - L.ae * v[r][M - 2]) * L.W1 - L.Q1 * g0w[r];
   }
-  double B = L.Q1 * L.Q0;
-  slot_scan_fwd<64, R>(F, B);
+  double BA = LA.Q1 * LA.Q0, BB = LB.Q1 * LB.Q0;
+  slot_scan_fwd<64, R, NA>(F, BA, BB);
   double Fin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Fin[r] = 0.0;
@@ -885,17 +923,18 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
     double* slots = lds;  // forward totals of the waves
     if (lane == 63) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) slots[wv * (R + 1) + r] = F[r];
-      slots[wv * (R + 1) + R] = B;
+      for (int r = 0; r < R; ++r) slots[wv * (R + 2) + r] = F[r];
+      slots[wv * (R + 2) + R] = BA;
+      slots[wv * (R + 2) + R + 1] = BB;
     }
     __syncthreads();
     for (int w = 0; w < wv; ++w) {
-      const double* q = slots + w * (R + 1);
+      const double* q = slots + w * (R + 2);
 #pragma unroll
-      for (int r = 0; r < R; ++r) Fin[r] = q[r] + q[R] * Fin[r];
+      for (int r = 0; r < R; ++r) Fin[r] = q[r] + q[r < NA ? R : R + 1] * Fin[r];
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) F[r] += B * Fin[r];
+    for (int r = 0; r < R; ++r) F[r] += (r < NA ? BA : BB) * Fin[r];
   }
   double Fprev[R];
 #pragma unroll
@@ -907,39 +946,37 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
   // backward recurrence
   double U[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) U[r] = g0w[r] - L.Q0 * Fprev[r] - L.C0 * F[r];
-  double E = L.C0 * L.C1;
-  slot_scan_bwd<64, R>(U, E);
+  for (int r = 0; r < R; ++r) U[r] = g0w[r] - ADI_TAB(r).Q0 * Fprev[r] - ADI_TAB(r).C0 * F[r];
+  double EA = LA.C0 * LA.C1, EB = LB.C0 * LB.C1;
+  slot_scan_bwd<64, R, NA>(U, EA, EB);
   double Uin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Uin[r] = 0.0;
   if constexpr (NW > 1) {
-    double* slots = lds + NW * (R + 1);  // backward totals (separate: no barrier between phases)
+    double* slots = lds + NW * (R + 2);  // backward totals (separate: no barrier between phases)
     if (lane == 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) slots[wv * (R + 1) + r] = U[r];
-      slots[wv * (R + 1) + R] = E;
+      for (int r = 0; r < R; ++r) slots[wv * (R + 2) + r] = U[r];
+      slots[wv * (R + 2) + R] = EA;
+      slots[wv * (R + 2) + R + 1] = EB;
     }
     __syncthreads();
     for (int w = NW - 1; w > wv; --w) {
-      const double* q = slots + w * (R + 1);
+      const double* q = slots + w * (R + 2);
 #pragma unroll
-      for (int r = 0; r < R; ++r) Uin[r] = q[r] + q[R] * Uin[r];
+      for (int r = 0; r < R; ++r) Uin[r] = q[r] + q[r < NA ? R : R + 1] * Uin[r];
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) U[r] += E * Uin[r];
+    for (int r = 0; r < R; ++r) U[r] += (r < NA ? EA : EB) * Uin[r];
   }
 
-  // chunk ends, their outer neighbours, interior back substitution
-  double xm1[R], xp1[R];
+  // chunk ends, interior back substitution
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     double un = __shfl_down(U[r], 1, 64);
     if (lane == 63) un = Uin[r];
     const double xs = U[r];
-    const double xe = F[r] - L.C1 * un;
-    xm1[r] = Fprev[r] - L.cprev * U[r];
-    xp1[r] = un;
+    const double xe = F[r] - ADI_TAB(r).C1 * un;
     v[r][0] = xs;
     v[r][M - 1] = xe;
     F[r] = xs;
@@ -948,17 +985,18 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], double (*o)[M], cons
 #pragma unroll
   for (int t = 1; t <= M - 2; ++t)
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r][t] = v[r][t] - L.sp[t] * F[r] - L.sr[t] * U[r];
+    for (int r = 0; r < R; ++r) v[r][t] = v[r][t] - ADI_TAB(r).sp[t] * F[r] - ADI_TAB(r).sr[t] * U[r];
+#undef ADI_TAB
+}
 
-  // next half step's right-hand side
-#pragma unroll
-  for (int t = 0; t < M; ++t)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double xl = t > 0 ? v[r][t > 0 ? t - 1 : 0] : xm1[r];
-      const double xr = t < M - 1 ? v[r][t < M - 1 ? t + 1 : t] : xp1[r];
-      o[r][t] = L.od[t] * v[r][t] + L.ol[t] * xl + L.ou[t] * xr + L.oc[t];
-    }
+// The next half step's right-hand side of line r of a block at chunk
+// offset t, from the solution x and the right-hand side d the line was
+// solved with: with a x[-1] + b x + c x[+1] = d the output operator
+// od x + ol x[-1] + ou x[+1] + oc (eq. 8-9: the explicit half of the
+// same direction) equals ok x - theta d + oc, so no neighbour is needed.
+// Outside the domain ok = oc = 0 and x = d = 0, so the result is 0.
+__device__ __forceinline__ double next_rhs(double ok, double oc, double theta, double x, double d) {
+  return fma(ok, x, fma(-theta, d, oc));
 }
 
 }  // namespace adi

@@ -6,6 +6,7 @@
 // (and, when asked, the solution).  Per step the field moves through HBM
 // exactly twice: 8 B read + 8 B written per active cell per half step.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -567,7 +568,19 @@ adi_status launch_init_rhs(adi_problem p) {
   return ADI_OK;
 }
 
-adi_status launch_strip_sweep(adi_problem p, int dir, const double* din, double* dout, double* xout) {
+// Launch a sweep kernel taking one argument struct; with events, they take
+// the kernel's own start and end times (no separate event packets).
+template <class Args>
+void launch_args(const void* fn, int grid, int threads, hipStream_t stream, Args& a, hipEvent_t e0, hipEvent_t e1) {
+  void* args[] = {&a};
+  if (e0 || e1)
+    (void)hipExtLaunchKernel(fn, dim3(grid), dim3(threads), args, 0, stream, e0, e1, 0);
+  else
+    (void)hipLaunchKernel(fn, dim3(grid), dim3(threads), args, 0, stream);
+}
+
+adi_status launch_strip_sweep(adi_problem p, int dir, const double* din, double* dout, double* xout,
+                              hipEvent_t e0, hipEvent_t e1) {
   const DirState& D = dir == 0 ? p->r : p->z;
   const DirState& X = dir == 0 ? p->z : p->r;
   StripArgs a;
@@ -581,16 +594,17 @@ adi_status launch_strip_sweep(adi_problem p, int dir, const double* din, double*
   a.strip = p->strip;
   a.nr = p->P.nr;
   a.nz = p->P.nz;
-  const int grid = strip_setup(a, p->ranges, dir, D.nlines, D.ncls, X.ncls);
+  const int grid = strip_setup(a, p->ranges, dir, D.nlines, D.ncls, X.ncls, p->P.theta);
   const StripVariant& V = kStrip[D.L.variant];
-  hipLaunchKernelGGL(V.fn, dim3(grid), dim3(64 * V.NW), 0, p->stream, a);
+  launch_args((const void*)V.fn, grid, 64 * V.NW, p->stream, a, e0, e1);
   ADI_CHECK_LAUNCH();
   return ADI_OK;
 }
 
-adi_status launch_sweep(adi_problem p, int dir, const double* din, double* dout, double* xout) {
+adi_status launch_sweep(adi_problem p, int dir, const double* din, double* dout, double* xout,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const DirState& D = dir == 0 ? p->r : p->z;
-  if (D.L.layout == ADI_LAYOUT_STRIPS) return launch_strip_sweep(p, dir, din, dout, xout);
+  if (D.L.layout == ADI_LAYOUT_STRIPS) return launch_strip_sweep(p, dir, din, dout, xout, e0, e1);
   SweepArgs a;
   a.din = din;
   a.dout = dout;
@@ -618,7 +632,7 @@ adi_status launch_sweep(adi_problem p, int dir, const double* din, double* dout,
   const Variant& V = kVariants[D.L.variant];
   const int threads = 64 * D.L.WPL * D.L.NGW;
   const int blocks = std::max(1, (a.ngroups + D.L.NGW - 1) / D.L.NGW);
-  hipLaunchKernelGGL(V.fn, dim3(blocks), dim3(threads), 0, p->stream, a);
+  launch_args((const void*)V.fn, blocks, threads, p->stream, a, e0, e1);
   ADI_CHECK_LAUNCH();
   return ADI_OK;
 }
@@ -1048,21 +1062,34 @@ adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_
   if (!(dt > 0.0)) return fail(ADI_EINVAL, "dt must be > 0");
   ADI_TRY(ensure_tables(p, dt));
   if (!p->rhs_valid) ADI_TRY(launch_init_rhs(p));
-  hipEvent_t ev[3];
-  for (auto& x : ev) ADI_HIP(hipEventCreate(&x));
+  // Half steps alternate as in a time step, so every sweep reads what the
+  // other direction has just written: r sweeps read the last z output (dA
+  // first) and write dB, z sweeps read dB and write mid; the carried state
+  // (dA, T) is untouched.  Every launch carries its own start and end events.
+  const size_t ne = 4 * (size_t)nlaunch;
+  std::vector<hipEvent_t> ev(ne, nullptr);
   adi_status st = ADI_OK;
-  // r sweeps read dA and write dB; z sweeps read dB and write scratch, so
-  // the carried state (dA, T) is untouched.
-  (void)hipEventRecord(ev[0], p->stream);
-  for (int i = 0; i < nlaunch && st == ADI_OK; ++i) st = launch_sweep(p, 0, p->dA, p->dB, nullptr);
-  (void)hipEventRecord(ev[1], p->stream);
-  for (int i = 0; i < nlaunch && st == ADI_OK; ++i) st = launch_sweep(p, 1, p->dB, p->mid, nullptr);
-  (void)hipEventRecord(ev[2], p->stream);
-  hipError_t e = hipEventSynchronize(ev[2]);
+  for (auto& x : ev)
+    if (hipEventCreate(&x) != hipSuccess) {
+      x = nullptr;
+      st = fail(ADI_EDEVICE, "hipEventCreate failed");
+      break;
+    }
+  for (int i = 0; i < nlaunch && st == ADI_OK; ++i) {
+    st = launch_sweep(p, 0, i == 0 ? p->dA : p->mid, p->dB, nullptr, ev[4 * i], ev[4 * i + 1]);
+    if (st == ADI_OK) st = launch_sweep(p, 1, p->dB, p->mid, nullptr, ev[4 * i + 2], ev[4 * i + 3]);
+  }
+  hipError_t e = hipStreamSynchronize(p->stream);
   float a = 0.f, b = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
-  if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[1], ev[2]);
-  for (auto& x : ev) (void)hipEventDestroy(x);
+  for (int i = 0; i < nlaunch && st == ADI_OK && e == hipSuccess; ++i) {
+    float x = 0.f, y = 0.f;
+    e = hipEventElapsedTime(&x, ev[4 * i], ev[4 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&y, ev[4 * i + 2], ev[4 * i + 3]);
+    a += x;
+    b += y;
+  }
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
   if (st != ADI_OK) return st;
   if (e != hipSuccess) return fail(ADI_EDEVICE, "event timing: %s", hipGetErrorString(e));
   if (ms_r) *ms_r = a / nlaunch;

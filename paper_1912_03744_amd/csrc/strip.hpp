@@ -4,6 +4,7 @@
 
 #include <stdint.h>
 
+
 #include "device.hpp"
 
 namespace adi {
@@ -44,10 +45,16 @@ struct StripArgs {
   int line_end[3];          // class of line l: number of q with l >= line_end[q]
   int pos_end[3];           // crossing class of position p: number of q with p >= pos_end[q]
   int nxcls;                // crossing classes
-  int nblocks;              // row groups (r sweep)
-  int nmix;                 // r sweep: row groups whose rows are not all of one band ...
-  int mix[4];               // ... solved one row per workgroup by nblocks + 4*m + row
+  int nblocks;              // row groups (r sweep) or strips (z sweep)
+  int nmix;                 // r sweep: row groups whose rows are not all of one band, solved
+  int mix[4];               //   one row per workgroup by nblocks + 4*m + row (mix[m]: group);
+                            // z sweep: extra workgroups nblocks + m, one per further class
+                            //   of a strip solved class by class (mix[m] = 4 * strip + class)
+  double theta;             // weight of the solved right-hand side in the next one (1 PR, 0 LOD-BE)
 };
+
+// LDS doubles of a workgroup's reduced-system carries (NW waves).
+__host__ __device__ constexpr int strip_carry(int NW) { return 2 * NW * 6; }
 
 // ---- host side: launch arguments shared by the library and its tests ----
 
@@ -67,18 +74,42 @@ __host__ __device__ inline void strip_class_ends(const int* ranges, int dir, int
   }
 }
 
+__host__ __device__ inline int class_at(const int* ends, int x) {
+  return (x >= ends[0]) + (x >= ends[1]) + (x >= ends[2]);
+}
+
+// Lines r < nact of a block of 4 starting at line0 whose class is c.
+__host__ __device__ inline unsigned block_lines_of(const StripArgs& a, int line0, int nact, int c) {
+  unsigned m = 0;
+  for (int r = 0; r < 4; ++r)
+    if (r < nact && class_at(a.line_end, line0 + r) == c) m |= 1u << r;
+  return m;
+}
+
+// A z strip (columns c0 .. c0+nact-1) whose columns split 3|1 or 1|3 between
+// two consecutive classes: solved in one pass with both classes' tables.
+__host__ __device__ inline bool strip_split(const StripArgs& a, int c0, int nact) {
+  const int c_lo = class_at(a.line_end, c0), c_hi = class_at(a.line_end, c0 + nact - 1);
+  const unsigned m = block_lines_of(a, c0, nact, c_lo);
+  const int na = (m & 1u) + ((m >> 1) & 1u) + ((m >> 2) & 1u) + ((m >> 3) & 1u);
+  return c_hi == c_lo + 1 && na != 2;
+}
+
 // Fill the class fields of a sweep's arguments and return its grid size.
 // dir 0 (r sweep): lines are rows (band classes), positions columns; row
 // groups straddling a band boundary get one workgroup per row.  dir 1 (z
 // sweep): lines are columns, positions rows; one workgroup per strip.
-inline int strip_setup(StripArgs& a, const int* ranges, int dir, int nlines, int ncls_lines, int ncls_pos) {
+// theta: 1 for Peaceman-Rachford, 0 for LOD backward Euler.
+inline int strip_setup(StripArgs& a, const int* ranges, int dir, int nlines, int ncls_lines, int ncls_pos,
+                       double theta) {
+  a.theta = theta;
   strip_class_ends(ranges, dir == 0 ? 0 : 1, ncls_lines, a.line_end);
   strip_class_ends(ranges, dir == 0 ? 1 : 0, ncls_pos, a.pos_end);
   a.nxcls = ncls_pos;
   a.nlines = nlines;
   a.nblocks = (nlines + 3) / 4;
   a.nmix = 0;
-  if (dir == 0)
+  if (dir == 0) {
     for (int q = 0; q < 3; ++q) {
       const int e = a.line_end[q];
       if (e <= 0 || e >= nlines || e % 4 == 0) continue;
@@ -86,8 +117,22 @@ inline int strip_setup(StripArgs& a, const int* ranges, int dir, int nlines, int
       for (int m = 0; m < a.nmix; ++m) seen = seen || a.mix[m] == e / 4;
       if (!seen) a.mix[a.nmix++] = e / 4;
     }
+    for (int m = a.nmix; m < 4; ++m) a.mix[m] = -1;
+    return a.nblocks + 4 * a.nmix;
+  }
+  // z sweep: every class boundary inside a strip that is not solved in one
+  // pass adds a workgroup for the class starting there
+  for (int q = 0; q < 3; ++q) {
+    const int e = a.line_end[q];
+    if (e <= 0 || e >= nlines || e % 4 == 0) continue;
+    const int s = e / 4, c0 = 4 * s, nact = nlines - c0 < 4 ? nlines - c0 : 4;
+    const int w = 4 * s + class_at(a.line_end, e);
+    bool seen = false;  // boundaries of empty classes coincide
+    for (int m = 0; m < a.nmix; ++m) seen = seen || a.mix[m] == w;
+    if (!seen && !strip_split(a, c0, nact)) a.mix[a.nmix++] = w;
+  }
   for (int m = a.nmix; m < 4; ++m) a.mix[m] = -1;
-  return a.nblocks + 4 * a.nmix;
+  return a.nblocks + a.nmix;
 }
 
 // r sweep work of a workgroup: b < nblocks is row group b with all its rows
@@ -115,23 +160,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int class_at(const int* ends, int x) {
-  return (x >= ends[0]) + (x >= ends[1]) + (x >= ends[2]);
-}
-
 // Add the crossing constants of the other direction to the outputs of the
-// lines in `mask`: for line line0 + r at position p, xc[class of p][line]
-// (uniform across the workgroup), at positions inside the domain.
+// block slots in `mask`: for line l at position p, xc[class of p][l]
+// (uniform across the workgroup), at positions inside the domain.  Slot r
+// holds line line0 + r, or line0 + 3 - r when `rev` is set.
 template <int M>
 __device__ __forceinline__ void add_crossing(const StripArgs& a, double (*o)[M], int line0, unsigned mask,
-                                             int n, int p0) {
+                                             int n, int p0, bool rev = false) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     if (!((mask >> r) & 1u)) continue;
+    const int line = line0 + (rev ? 3 - r : r);
     double xcv[MAX_CLS];
 #pragma unroll
-    for (int c = 0; c < MAX_CLS; ++c) xcv[c] = c < a.nxcls ? a.xc[(long)c * a.nlines + line0 + r] : 0.0;
-    const LineTab& tb = a.tabs[class_at(a.line_end, line0 + r)];
+    for (int c = 0; c < MAX_CLS; ++c) xcv[c] = c < a.nxcls ? a.xc[(long)c * a.nlines + line] : 0.0;
+    const LineTab& tb = a.tabs[class_at(a.line_end, line)];
     const unsigned long long live = chunk_live_mask(p0, M, n, tb.skip_lo, tb.skip_hi);
 #pragma unroll
     for (int t = 0; t < M; ++t) {
@@ -141,61 +184,34 @@ __device__ __forceinline__ void add_crossing(const StripArgs& a, double (*o)[M],
   }
 }
 
-// Solve the 4 lines of a block and hand each line's outputs to `emit`
-// (v: solution, o: next right-hand side, mask of the lines to take).  Lines
-// of one class are solved together; a block whose lines span several classes
-// (classes grow with the line index) is solved once per class, each pass
-// refetching the block's right-hand side with `fetch`.  L: the tables of the
-// first class, already loaded; later passes reload it.
-template <int M, int NW, class Fetch, class Emit>
-__device__ __forceinline__ void solve_block(const StripArgs& a, double (*v)[M], int line0, int nact, int n, int tid,
-                                            double* carry, LaneTab<M>& L, Fetch fetch, Emit emit) {
-  const int p0 = tid * M;
-  const int c_lo = class_at(a.line_end, line0), c_hi = class_at(a.line_end, line0 + nact - 1);
-  auto lines_of = [&](int c) {
-    unsigned mine = 0;
+// The next right-hand side of the lines of a block in `mask`, in place
+// (v: solution on entry, the outputs on return), from the right-hand sides
+// d the block was solved with: lines r < NA have the tables LA, the others
+// LB.  `rhs(r, t)` returns d of line r at chunk offset t.
+template <int M, int NA, class Rhs>
+__device__ __forceinline__ void block_outputs(const StripArgs& a, double (*v)[M], const LaneTab<M>& LA,
+                                              const LaneTab<M>& LB, unsigned mask, Rhs rhs) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (r < nact && class_at(a.line_end, line0 + r) == c) mine |= 1u << r;
-    return mine;
-  };
-  for (int c = c_lo; c <= c_hi; ++c) {
-    const LineTab& tb = a.tabs[c];
-    if (c > c_lo) {
-      load_lanetab<M, 64 * NW>(L, tb.pos, tb.chk, tid);  // L held the first class
-      fetch(v);
+  for (int r = 0; r < 4; ++r)
+    if ((mask >> r) & 1u) {
+      const LaneTab<M>& L = r < NA ? LA : LB;
+#pragma unroll
+      for (int t = 0; t < M; ++t) v[r][t] = next_rhs(L.ok[t], L.oc[t], a.theta, v[r][t], rhs(r, t));
     }
-    double o[4][M];
-    solve_lanes<M, NW, 4>(v, o, L, chunk_live_mask(p0, M, n, tb.skip_lo, tb.skip_hi), carry);
-    emit(v, o, lines_of(c));
-  }
 }
 
-// Each lane reads and writes only its own chunk's LDS slots between the
-// staging copies, which each wave does for its own chunks.
-// The z-sweep work on strip s by lanes tid = 0 .. 64*NW-1 (a workgroup, or
-// one wave when NW = 1), staging through buf (64*NW*4*M doubles) and
-// carrying through `carry` (2*NW*5 doubles).
-template <int M, int NW>
-__device__ __forceinline__ void strip_z_body(const StripArgs& a, int s, int tid, double* buf, double* carry) {
-  constexpr int NT = 64 * NW;
-  constexpr int CH = 4 * M;  // LDS doubles per chunk (rows of 4, no padding)
-  const int c0 = 4 * s;
-  const int nact = min(4, a.nr - c0);
-  const int p0 = tid * M;
-  // factor tables of the first class ahead of the data
-  LaneTab<M> L0;
-  {
-    const LineTab& tb = a.tabs[class_at(a.line_end, c0)];
-    load_lanetab<M, NT>(L0, tb.pos, tb.chk, tid);
-  }
-  // each wave stages the 64*M rows of its own 64 chunks (contiguous in the
-  // strip) through its own LDS region
+// z-sweep building blocks.  Lane tid of a strip's workgroup owns chunk tid:
+// rows [tid*M, tid*M+M) of the strip's 4 columns, staged by its wave (each
+// wave copies the 64*M rows of its own 64 chunks, contiguous in the strip,
+// through its own LDS region) into its own LDS slots (4*M doubles, laid out
+// as in the strip).  Each lane reads and writes only its own slots between
+// the staging copies.
+
+template <int M>
+__device__ __forceinline__ void stage_z(const StripArgs& a, int s, int tid, double* buf) {
   const int lane = tid & 63, wrow0 = (tid >> 6) * 64 * M;
-  double* wbuf = buf + (tid >> 6) * 64 * CH;
+  double* wbuf = buf + (tid >> 6) * 64 * 4 * M;
   const double2* __restrict__ src = (const double2*)(a.din + (long)s * a.strip) + 2 * wrow0;
-  // with 4*M doubles per chunk, local row jl sits at 4*jl in the wave's
-  // region, as in the strip: the copy is contiguous
 #pragma unroll
   for (int u = 0; u < 2 * M; ++u) {
     const int q = lane + u * 64;  // local row q/2, column pair q%2
@@ -203,64 +219,156 @@ __device__ __forceinline__ void strip_z_body(const StripArgs& a, int s, int tid,
     if (wrow0 + (q >> 1) < a.nz) x = src[q];
     *(double2*)&wbuf[2 * q] = x;
   }
-  wave_sync();
-  double* mine_slots = buf + tid * CH;
-  auto fetch = [&](double (*v)[M]) {
+}
+
+// Store the wave's rows back: whole rows, or only the columns in colmask.
+template <int M>
+__device__ __forceinline__ void store_z(const StripArgs& a, int s, int tid, const double* buf, unsigned colmask) {
+  const int lane = tid & 63, wrow0 = (tid >> 6) * 64 * M;
+  const double* wbuf = buf + (tid >> 6) * 64 * 4 * M;
+  double2* __restrict__ dst = (double2*)(a.dout + (long)s * a.strip) + 2 * wrow0;
+  if (colmask == 0xfu) {
 #pragma unroll
-    for (int t = 0; t < M; ++t) {
-      const double2 lo = *(const double2*)&mine_slots[t * 4];
-      const double2 hi = *(const double2*)&mine_slots[t * 4 + 2];
+    for (int u = 0; u < 2 * M; ++u) {
+      const int q = lane + u * 64;
+      if (wrow0 + (q >> 1) < a.nz) dst[q] = *(const double2*)&wbuf[2 * q];
+    }
+  } else {
+    double* __restrict__ d1 = (double*)dst;
+    for (int u = 0; u < 2 * M; ++u) {
+      const int q = lane + u * 64, c = 2 * (q & 1);
+      if (wrow0 + (q >> 1) < a.nz) {
+        if ((colmask >> c) & 1u) d1[2 * q] = wbuf[2 * q];
+        if ((colmask >> (c + 1)) & 1u) d1[2 * q + 1] = wbuf[2 * q + 1];
+      }
+    }
+  }
+}
+
+// Solve the strip's columns with slots r < NA on LA, the rest on LB, and put
+// the next right-hand side of the slots in `mask` into the lane's LDS
+// slots (and the solution into xout).  Slot r holds column c0 + r, or
+// c0 + 3 - r when `rv` is set (NA < 4 only).
+template <int M, int NW, int NA>
+__device__ __forceinline__ void z_pass(const StripArgs& a, int c0, int tid, double* mine_slots, const LaneTab<M>& LA,
+                                       const LaneTab<M>& LB, double* carry, bool rv, unsigned mask) {
+  const bool rev = NA < 4 && rv;
+  const int p0 = tid * M;
+  auto col = [&](int r) { return rev ? 3 - r : r; };
+  double v[4][M];
+#pragma unroll
+  for (int t = 0; t < M; ++t) {
+    const double2 lo = *(const double2*)&mine_slots[t * 4];
+    const double2 hi = *(const double2*)&mine_slots[t * 4 + 2];
+    if (rev) {
+      v[0][t] = hi.y; v[1][t] = hi.x; v[2][t] = lo.y; v[3][t] = lo.x;
+    } else {
       v[0][t] = lo.x; v[1][t] = lo.y; v[2][t] = hi.x; v[3][t] = hi.y;
     }
-  };
-  auto emit = [&](double (*v)[M], double (*o)[M], unsigned mask) {
-    if (a.xc) add_crossing<M>(a, o, c0, mask, a.nz, p0);
-    if (mask == 0xfu) {
+  }
+  solve_lanes<M, NW, 4, NA>(v, LA, LB, carry);
+  if (a.xout)
 #pragma unroll
-      for (int t = 0; t < M; ++t) {
-        *(double2*)&mine_slots[t * 4] = make_double2(o[0][t], o[1][t]);
-        *(double2*)&mine_slots[t * 4 + 2] = make_double2(o[2][t], o[3][t]);
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < M; ++t)
+    for (int t = 0; t < M; ++t)
+      if (p0 + t < a.nz)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if ((mask >> r) & 1u) mine_slots[t * 4 + r] = o[r][t];
+          if ((mask >> r) & 1u) a.xout[(long)(p0 + t) * a.nr + c0 + col(r)] = v[r][t];
+  block_outputs<M, NA>(a, v, LA, LB, mask, [&](int r, int t) { return mine_slots[t * 4 + col(r)]; });
+  if (a.xc) add_crossing<M>(a, v, c0, mask, a.nz, p0, rev);
+  if (mask == 0xfu && !rev) {
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      *(double2*)&mine_slots[t * 4] = make_double2(v[0][t], v[1][t]);
+      *(double2*)&mine_slots[t * 4 + 2] = make_double2(v[2][t], v[3][t]);
     }
-    if (a.xout)
+  } else {
 #pragma unroll
-      for (int t = 0; t < M; ++t)
-        if (p0 + t < a.nz)
+    for (int t = 0; t < M; ++t)
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            if ((mask >> c) & 1u) a.xout[(long)(p0 + t) * a.nr + c0 + c] = v[c][t];
-  };
-  double v[4][M];
-  fetch(v);
-  // columns past the grid's edge hold 0
+      for (int r = 0; r < 4; ++r)
+        if ((mask >> r) & 1u) mine_slots[t * 4 + col(r)] = v[r][t];
+  }
+}
+
+// Columns past the grid's edge hold 0 in the lane's slots.
+template <int M>
+__device__ __forceinline__ void zero_past_edge(double* mine_slots, int nact) {
 #pragma unroll
   for (int t = 0; t < M; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       if (r >= nact) mine_slots[t * 4 + r] = 0.0;
-  solve_block<M, NW>(a, v, c0, nact, a.nz, tid, carry, L0, fetch, emit);
+}
+
+// The z-sweep work on strip s by lanes tid = 0 .. 64*NW-1 (a workgroup, or
+// one wave when NW = 1), staging through buf (64*NW*4*M doubles) and
+// carrying through `carry` (strip_carry(NW) doubles), one pass per class
+// of the strip's columns (used by the batch).
+template <int M, int NW>
+__device__ __forceinline__ void strip_z_body(const StripArgs& a, int s, int tid, double* buf, double* carry) {
+  constexpr int NT = 64 * NW;
+  const int c0 = 4 * s;
+  const int nact = min(4, a.nr - c0);
+  const int c_lo = class_at(a.line_end, c0), c_hi = class_at(a.line_end, c0 + nact - 1);
+  stage_z<M>(a, s, tid, buf);
+  LaneTab<M> L;  // behind the data loads
+  load_lanetab<M, NT>(L, a.tabs[c_lo].pos, a.tabs[c_lo].chk, tid);
   wave_sync();
-  double2* __restrict__ dst = (double2*)(a.dout + (long)s * a.strip) + 2 * wrow0;
-#pragma unroll
-  for (int u = 0; u < 2 * M; ++u) {
-    const int q = lane + u * 64;
-    if (wrow0 + (q >> 1) < a.nz) dst[q] = *(const double2*)&wbuf[2 * q];
+  double* mine_slots = buf + tid * 4 * M;
+  zero_past_edge<M>(mine_slots, nact);
+  for (int c = c_lo; c <= c_hi; ++c) {
+    if (c > c_lo) load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
+    z_pass<M, NW, 4>(a, c0, tid, mine_slots, L, L, carry, false, block_lines_of(a, c0, nact, c));
   }
+  wave_sync();
+  store_z<M>(a, s, tid, buf, 0xfu);
 }
 
 // z sweep: workgroup per strip (4 adjacent columns), lane k holds rows
-// [kM, kM+M) of the strip's columns.
+// [kM, kM+M) of the strip's columns.  A strip of one class, or split 3|1 or
+// 1|3 between two classes (both classes' tables, slots 0..2 on the first,
+// columns in reverse order for 1|3), is solved in one pass; in any other
+// strip spanning several classes this workgroup solves the first class and
+// extra workgroups (nblocks + m) one further class each, every one storing
+// only its own columns.
 template <int M, int NW>
 __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
-  __shared__ __align__(16) double buf[64 * NW * 4 * M];
-  __shared__ double carry[2 * NW * 5];
-  strip_z_body<M, NW>(a, xcd_block(blockIdx.x, gridDim.x), threadIdx.x, buf, carry);
+  constexpr int NT = 64 * NW;
+  __shared__ __align__(16) double buf[NT * 4 * M];
+  __shared__ double carry[strip_carry(NW)];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x;
+  const int s = b < a.nblocks ? b : a.mix[b - a.nblocks] >> 2;
+  const int c0 = 4 * s;
+  const int nact = min(4, a.nr - c0);
+  const int c_lo = class_at(a.line_end, c0), c_hi = class_at(a.line_end, c0 + nact - 1);
+  const unsigned all = nact == 4 ? 0xfu : (1u << nact) - 1u;
+  const bool split = c_hi == c_lo + 1 && strip_split(a, c0, nact);
+  const bool rev = split && block_lines_of(a, c0, nact, c_lo) == 1u;
+  // this workgroup's class (one-class passes) and its columns
+  const int c = b < a.nblocks ? c_lo : a.mix[b - a.nblocks] & 3;
+  const unsigned mine = c_lo == c_hi ? all : block_lines_of(a, c0, nact, c);
+  // data loads first: waiting for them then does not wait for the tables
+  stage_z<M>(a, s, tid, buf);
+  LaneTab<M> LA, LB;
+  {
+    const int ca = rev ? c_hi : c;
+    load_lanetab<M, NT>(LA, a.tabs[ca].pos, a.tabs[ca].chk, tid);
+    if (split) load_lanetab<M, NT>(LB, a.tabs[rev ? c_lo : c_hi].pos, a.tabs[rev ? c_lo : c_hi].chk, tid);
+  }
+  wave_sync();
+  double* mine_slots = buf + tid * 4 * M;
+  zero_past_edge<M>(mine_slots, nact);
+  if (split) {
+    // slot mask of the active columns
+    const unsigned m = rev ? ((all & 1u) << 3) | ((all & 2u) << 1) | ((all & 4u) >> 1) | ((all & 8u) >> 3) : all;
+    z_pass<M, NW, 3>(a, c0, tid, mine_slots, LA, LB, carry, rev, m);
+  } else {
+    z_pass<M, NW, 4>(a, c0, tid, mine_slots, LA, LA, carry, false, mine);
+  }
+  wave_sync();
+  store_z<M>(a, s, tid, buf, split || c_lo == c_hi ? 0xfu : mine);
 }
 
 // The r-sweep work on row group J by lanes tid = 0 .. 64*NW-1, solving the
@@ -275,11 +383,9 @@ __device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid,
   const int j0 = 4 * J;
   const int nact = min(4, a.nz - j0);
   const int p0 = tid * M;
-  LaneTab<M> L0;
-  {
-    const LineTab& tb = a.tabs[class_at(a.line_end, j0)];
-    load_lanetab<M, NT>(L0, tb.pos, tb.chk, tid);
-  }
+  const int c_lo = class_at(a.line_end, j0), c_hi = class_at(a.line_end, j0 + nact - 1);
+  LaneTab<M> L;
+  load_lanetab<M, NT>(L, a.tabs[c_lo].pos, a.tabs[c_lo].chk, tid);
   const int nstrips = (a.nr + 3) >> 2;
   const int lane = tid & 63, wst0 = (tid >> 6) * 64;
 #pragma unroll
@@ -292,22 +398,24 @@ __device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid,
   }
   wave_sync();
   double* mine_slots = buf + tid * CH;
-  auto fetch = [&](double (*v)[M]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r >= nact) {
+      *(double2*)&mine_slots[r * 4] = make_double2(0.0, 0.0);
+      *(double2*)&mine_slots[r * 4 + 2] = make_double2(0.0, 0.0);
+    }
+  auto rhs = [&](int r, int t) { return mine_slots[r * 4 + t]; };
+  for (int c = c_lo; c <= c_hi; ++c) {
+    if (c > c_lo) load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
+    const unsigned mask = block_lines_of(a, j0, nact, c);
+    double v[4][M];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const double2 lo = *(const double2*)&mine_slots[r * 4];
       const double2 hi = *(const double2*)&mine_slots[r * 4 + 2];
       v[r][0] = lo.x; v[r][1] = lo.y; v[r][2] = hi.x; v[r][3] = hi.y;
     }
-  };
-  auto emit = [&](double (*v)[M], double (*o)[M], unsigned mask) {
-    if (a.xc) add_crossing<M>(a, o, j0, mask, a.nr, p0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if ((mask >> r) & 1u) {
-        *(double2*)&mine_slots[r * 4] = make_double2(o[r][0], o[r][1]);
-        *(double2*)&mine_slots[r * 4 + 2] = make_double2(o[r][2], o[r][3]);
-      }
+    solve_lanes<M, NW, 4, 4>(v, L, L, carry);
     if (a.xout) {
       const int i0 = 4 * tid;
 #pragma unroll
@@ -317,16 +425,15 @@ __device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid,
           for (int t = 0; t < M; ++t)
             if (i0 + t < a.nr) a.xout[(long)(j0 + r) * a.nr + i0 + t] = v[r][t];
     }
-  };
-  double v[4][M];
-  fetch(v);
+    block_outputs<M, 4>(a, v, L, L, mask, rhs);
+    if (a.xc) add_crossing<M>(a, v, j0, mask, a.nr, p0);
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (r >= nact) {
-      *(double2*)&mine_slots[r * 4] = make_double2(0.0, 0.0);
-      *(double2*)&mine_slots[r * 4 + 2] = make_double2(0.0, 0.0);
-    }
-  solve_block<M, NW>(a, v, j0, nact, a.nr, tid, carry, L0, fetch, emit);
+    for (int r = 0; r < 4; ++r)
+      if ((mask >> r) & 1u) {
+        *(double2*)&mine_slots[r * 4] = make_double2(v[r][0], v[r][1]);
+        *(double2*)&mine_slots[r * 4 + 2] = make_double2(v[r][2], v[r][3]);
+      }
+  }
   wave_sync();
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -348,7 +455,7 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
   constexpr int NT = 64 * NW;
   constexpr int CH = 18;  // a 16-double tile + 2 pad
   __shared__ __align__(16) double buf[NT * CH];
-  __shared__ double carry[2 * NW * 5];
+  __shared__ double carry[strip_carry(NW)];
   int J, lc;
   if (!strip_work(a, xcd_block(blockIdx.x, gridDim.x), &J, &lc)) return;
   const int tid = threadIdx.x;
@@ -358,9 +465,6 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
   const int line0 = lc < 0 ? j0 : j0 + lc;
   const LineTab& tb = a.tabs[class_at(a.line_end, line0)];
   const int p0 = tid * M;
-  LaneTab<M> L;
-  load_lanetab<M, NT>(L, tb.pos, tb.chk, tid);
-  const unsigned long long live = chunk_live_mask(p0, M, a.nr, tb.skip_lo, tb.skip_hi);
   const int nstrips = (a.nr + 3) >> 2;
   // each wave stages the 64 tiles of its own chunks through its own LDS region
   const int lane = tid & 63, wst0 = (tid >> 6) * 64;
@@ -372,24 +476,36 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
     if (st < nstrips) x = *(const double2*)(a.din + (long)st * a.strip + (long)j0 * 4 + (q & 7) * 2);
     *(double2*)&buf[st * CH + (q & 7) * 2] = x;
   }
+  LaneTab<M> L;  // behind the data loads
+  load_lanetab<M, NT>(L, tb.pos, tb.chk, tid);
   wave_sync();
   double* mine_slots = buf + tid * CH;
   if (lc < 0) {
-    double v[4][M], o[4][M];
+    double v[4][M];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const double2 lo = *(const double2*)&mine_slots[r * 4];
       const double2 hi = *(const double2*)&mine_slots[r * 4 + 2];
       v[r][0] = lo.x; v[r][1] = lo.y; v[r][2] = hi.x; v[r][3] = hi.y;
     }
-    solve_lanes<M, NW, 4>(v, o, L, live, carry);
+    solve_lanes<M, NW, 4, 4>(v, L, L, carry);
     const unsigned mask = nact == 4 ? 0xfu : (1u << nact) - 1u;
-    if (a.xc) add_crossing<M>(a, o, j0, mask, a.nr, p0);
+    if (a.xout) {
+      const int i0 = 4 * tid;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < nact)
+#pragma unroll
+          for (int t = 0; t < M; ++t)
+            if (i0 + t < a.nr) a.xout[(long)(j0 + r) * a.nr + i0 + t] = v[r][t];
+    }
+    block_outputs<M, 4>(a, v, L, L, mask, [&](int r, int t) { return mine_slots[r * 4 + t]; });
+    if (a.xc) add_crossing<M>(a, v, j0, mask, a.nr, p0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const bool on = r < nact;
-      *(double2*)&mine_slots[r * 4] = make_double2(on ? o[r][0] : 0.0, on ? o[r][1] : 0.0);
-      *(double2*)&mine_slots[r * 4 + 2] = make_double2(on ? o[r][2] : 0.0, on ? o[r][3] : 0.0);
+      const bool on = r < nact;  // rows past the grid's edge hold 0
+      *(double2*)&mine_slots[r * 4] = make_double2(on ? v[r][0] : 0.0, on ? v[r][1] : 0.0);
+      *(double2*)&mine_slots[r * 4 + 2] = make_double2(on ? v[r][2] : 0.0, on ? v[r][3] : 0.0);
     }
     wave_sync();
 #pragma unroll
@@ -400,39 +516,24 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
         *(double2*)(a.dout + (long)st * a.strip + (long)j0 * 4 + (q & 7) * 2) =
             *(const double2*)&buf[st * CH + (q & 7) * 2];
     }
-    if (a.xout) {
-      const int i0 = 4 * tid;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r < nact)
-#pragma unroll
-          for (int t = 0; t < M; ++t)
-            if (i0 + t < a.nr) a.xout[(long)(j0 + r) * a.nr + i0 + t] = v[r][t];
-    }
   } else {
     // one row of a mixed row group
-    double v[1][M], o[1][M];
+    double v[4][M];
 #pragma unroll
     for (int t = 0; t < M; ++t) v[0][t] = mine_slots[lc * 4 + t];
-    solve_lanes<M, NW, 1>(v, o, L, live, carry);
-    if (a.xc) {
-      double o4[4][M];
+    solve_lanes<M, NW, 1, 1>(v, L, L, carry);
+    if (a.xout && tid < nstrips) {
+      const int i0 = 4 * tid;
 #pragma unroll
-      for (int t = 0; t < M; ++t) o4[0][t] = o[0][t], o4[1][t] = o4[2][t] = o4[3][t] = 0.0;
-      add_crossing<M>(a, o4, line0, 1u, a.nr, p0);
-#pragma unroll
-      for (int t = 0; t < M; ++t) o[0][t] = o4[0][t];
+      for (int t = 0; t < M; ++t)
+        if (i0 + t < a.nr) a.xout[(long)line0 * a.nr + i0 + t] = v[0][t];
     }
+    block_outputs<M, 4>(a, v, L, L, 1u, [&](int, int t) { return mine_slots[lc * 4 + t]; });
+    if (a.xc) add_crossing<M>(a, v, line0, 1u, a.nr, p0);
     if (tid < nstrips) {
       double* __restrict__ d = a.dout + (long)tid * a.strip + (long)line0 * 4;
-      *(double2*)d = make_double2(o[0][0], o[0][1]);
-      *(double2*)(d + 2) = make_double2(o[0][2], o[0][3]);
-      if (a.xout) {
-        const int i0 = 4 * tid;
-#pragma unroll
-        for (int t = 0; t < M; ++t)
-          if (i0 + t < a.nr) a.xout[(long)line0 * a.nr + i0 + t] = v[0][t];
-      }
+      *(double2*)d = make_double2(v[0][0], v[0][1]);
+      *(double2*)(d + 2) = make_double2(v[0][2], v[0][3]);
     }
   }
 }

@@ -70,30 +70,52 @@ inline double __shfl_down(double v, int d, int w = 64) {
   return __longlong_as_double(emu_exchange(__double_as_longlong(v), lane + d, lane + d < w, __double_as_longlong(v)));
 }
 // DPP controls used by the kernels: row_shl:1-15, row_shr:1-15,
-// row_bcast:15, row_bcast:31; lanes whose row is not in row_mask or whose
-// source is out of range keep `old` (bound_ctrl off).
-inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+// row_bcast:15, row_bcast:31.  emu_dpp_source gives the source lane and
+// whether the lane is written (row in row_mask, source in range).
+inline bool emu_dpp_source(int ctrl, int row_mask, int* sl) {
   const int lane = threadIdx.x & 63, inrow = lane & 15, row = lane >> 4;
-  int sl = lane;
   bool ok = true;
+  *sl = lane;
   if (ctrl >= 0x101 && ctrl <= 0x10f) {
     ok = inrow + (ctrl - 0x100) < 16;
-    sl = lane + (ctrl - 0x100);
+    *sl = lane + (ctrl - 0x100);
   } else if (ctrl >= 0x111 && ctrl <= 0x11f) {
     ok = inrow >= ctrl - 0x110;
-    sl = lane - (ctrl - 0x110);
+    *sl = lane - (ctrl - 0x110);
   } else if (ctrl == 0x142) {
     ok = row >= 1;
-    sl = 16 * row - 1;
+    *sl = 16 * row - 1;
   } else if (ctrl == 0x143) {
     ok = row >= 2;
-    sl = 31;
+    *sl = 31;
   } else {
     fprintf(stderr, "dpp control %#x is not emulated\n", ctrl);
     abort();
   }
   if (!((row_mask >> row) & 1)) ok = false;
-  return (int)emu_exchange(src, ok ? sl : lane, ok, old);
+  if (!ok) *sl = lane;
+  return ok;
+}
+// Lanes not written keep `old` (bound_ctrl off).
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+  int sl;
+  const bool ok = emu_dpp_source(ctrl, row_mask, &sl);
+  if (bound_ctrl) {
+    fprintf(stderr, "update_dpp with bound_ctrl is not emulated\n");
+    abort();
+  }
+  return (int)emu_exchange(src, sl, ok, old);
+}
+// All rows written (row_mask 0xf); lanes whose source is out of range read 0
+// (bound_ctrl on).
+inline int __builtin_amdgcn_mov_dpp(int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+  if (row_mask != 0xf || !bound_ctrl) {
+    fprintf(stderr, "mov_dpp is emulated for row_mask 0xf with bound_ctrl only\n");
+    abort();
+  }
+  int sl;
+  const bool ok = emu_dpp_source(ctrl, row_mask, &sl);
+  return (int)emu_exchange(src, sl, ok, 0);
 }
 inline int __builtin_amdgcn_readlane(int v, int l) { return (int)emu_exchange(v, l, true, 0); }
 inline int atomicAdd(int* p, int v) { return reinterpret_cast<std::atomic<int>*>(p)->fetch_add(v); }

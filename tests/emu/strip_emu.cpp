@@ -94,7 +94,7 @@ int run(Params P, double dt, int nsteps, int scheme, double T0, const char* out)
     for (int c = 0; c < MAX_CLS; ++c) a.tabs[c] = D[dir].tabs[c];
     a.xc = ambient ? D[1 - dir].xc.data() : nullptr;
     a.strip = strip; a.nr = nr; a.nz = nz;
-    *grid = strip_setup(a, ranges, dir, dir == 0 ? nz : nr, D[dir].ncls, D[1 - dir].ncls);
+    *grid = strip_setup(a, ranges, dir, dir == 0 ? nz : nr, D[dir].ncls, D[1 - dir].ncls, P.theta);
     return a;
   };
   for (int s = 0; s < nsteps; ++s) {

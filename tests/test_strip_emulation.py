@@ -5,7 +5,8 @@ barriers for LDS, shuffles, DPP row operations and readlane), against the
 oracle.  Checks the kernels' logic on the CPU: partial strips and row
 groups, strips and row groups that straddle class boundaries, cells outside
 the domain, non-zero ambient temperatures, both schemes, one and two waves
-per line."""
+per line, strips solved in one pass with two classes' tables (3|1 and
+1|3) and strips split between workgroups."""
 import os
 import shutil
 import subprocess
@@ -53,6 +54,9 @@ CASES = [
     ("seeded_37x91_pr", W.production(3, nr=37, nz=91).replace(dt=2e-3), 5, (1, 3, 1)),
     ("two_waves_150x333_pr", W.production(3, nr=150, nz=333).replace(dt=2e-3), 3, (1, 5, 2)),
     ("two_waves_r_150x333_lod", tiny_spec(nr=150, nz=333, scheme="lod", dt=0.02), 2, (2, 5, 2)),
+    # strips split 1|3 (reverse slot order), 3|1 and 2|2, with ambient films
+    ("splits_ambient_128x140_pr",
+     W.production(5, nr=128, nz=140).replace(dt=2e-3, t_inf=(0.0, 0.3, -0.2, 0.1), T0=0.2), 4, (1, 3, 1)),
 ]
 
 
