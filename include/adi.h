@@ -205,9 +205,12 @@ void adi_destroy(adi_problem p);
 /* A batch of n independent instances (the design sweep): instance i has its
  * own geometry geoms[i] (uniform grid, 3 <= nr <= 192, 3 <= nz <= 480;
  * face arrays are not supported here) and films bcs[i].  All instances are
- * advanced together by one persistent kernel launch: each workgroup takes
- * the next instance from an atomic queue (largest grids first), builds its
- * geometry and factor tables, runs the whole time loop and takes the next.
+ * advanced together, in one of two ways chosen by adi_batch_set_launch: one
+ * persistent kernel launch, where each workgroup takes the next instance
+ * from an atomic queue (largest grids first), builds its geometry and factor
+ * tables, runs the whole time loop and takes the next; or batched sweep
+ * launches, one per half step over all instances (one per z chunk shape),
+ * with one single-wave workgroup per block of 4 lines of any instance.
  * Errors: ADI_EINVAL, ADI_EUNSUPPORTED (grid or face arrays), ADI_ENOMEM. */
 adi_status adi_create_batch(int32_t n, const adi_geometry* geoms, const adi_bc* bcs, adi_scheme scheme,
                             void* hip_stream, adi_batch* out);
@@ -219,11 +222,13 @@ adi_status adi_batch_set_materials(adi_batch b, const double* k, const double* r
 /* Uniform initial temperature per instance (n values; NULL = all 0). */
 adi_status adi_batch_set_initial(adi_batch b, const double* T0);
 
-/* Launch shape of the batch kernel (the autotuner uses it): lines per lane
- * (1 or 2: right-hand sides by rows, line slots of 16 or 32 chunks; 4: right-
- * hand sides in strips of 4 columns, one wave per block of 4 lines), waves
- * per workgroup (4 or 8), resident workgroups per compute unit (1..8).
- * ADI_EUNSUPPORTED for shapes not compiled. */
+/* Launch shape of the batch (the autotuner uses it): lines per lane (1 or
+ * 2: right-hand sides by rows, line slots of 16 or 32 chunks; 4: right-hand
+ * sides in strips of 4 columns, one wave per block of 4 lines), waves per
+ * workgroup (4 or 8: the persistent kernel; 1, with 4 lines per lane: the
+ * batched sweep launches, each instance keeping its own right-hand sides and
+ * scratch), resident workgroups per compute unit (1..8; persistent kernel
+ * only).  ADI_EUNSUPPORTED for shapes not compiled. */
 adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t waves_per_block,
                                 int32_t blocks_per_cu);
 
@@ -232,7 +237,8 @@ adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t wav
  * terminal-face profile (top row resampled at r_k = (k+0.5)*rmax/npts, as in
  * adi_read_profile) after every snapshot_every-th step (0 = none).  Enqueued
  * on the batch's stream as one captured HIP graph (queue reset + persistent
- * kernel); returns without waiting. */
+ * kernel, or the instance set-up and every sweep launch of the nsteps
+ * steps); returns without waiting. */
 adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapshot_every, int32_t npts);
 
 /* Wait for the batch's stream. */

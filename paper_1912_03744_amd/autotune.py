@@ -142,7 +142,7 @@ def apply(problem, dt, scheme, retune=False, verbose=False, log=None):
 # compiled batch kernels: (lines per lane, waves per workgroup), 4 lines
 # per lane being the strip-layout kernel; resident workgroups per compute
 # unit is a launch parameter
-BATCH_KERNELS = ((1, 4), (2, 4), (1, 8), (2, 8), (4, 4), (4, 8))
+BATCH_KERNELS = ((1, 4), (2, 4), (1, 8), (2, 8), (4, 4), (4, 8), (4, 1))
 BATCH_BLOCKS_PER_CU = (1, 2, 4)
 
 
@@ -160,7 +160,8 @@ def tune_batch(batch, dt, nsteps=100, verbose=False, log=None):
     "trials": [...]}."""
     trials, best = [], None
     for r, nw in BATCH_KERNELS:
-        for bpc in BATCH_BLOCKS_PER_CU:
+        # one wave per workgroup: batched sweep launches, no persistent workgroups
+        for bpc in (BATCH_BLOCKS_PER_CU if nw > 1 else (1,)):
             batch.set_launch(r, nw, bpc)
             batch.time(dt, nsteps, 1)  # first call allocates the workgroup scratch
             t = batch.time(dt, nsteps, 1)

@@ -201,10 +201,11 @@ struct BatchVariant {
   BatchFn fn;
 };
 // R = 1, 2: rows-layout line solver; R = 4: the strip-layout kernel
-// (4 lines per lane, one wave per block of lines).
+// (4 lines per lane, one wave per block of lines); R = 4 with one wave per
+// workgroup: batched sweep launches (no persistent kernel).
 static const BatchVariant kBatchVariants[] = {
     {1, 4, k_batch<1, 4>}, {2, 4, k_batch<2, 4>}, {1, 8, k_batch<1, 8>}, {2, 8, k_batch<2, 8>},
-    {4, 4, k_batch_s<4>},  {4, 8, k_batch_s<8>},
+    {4, 4, k_batch_s<4>},  {4, 8, k_batch_s<8>},  {4, 1, nullptr},
 };
 static const int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 
@@ -276,6 +277,16 @@ struct adi_batch_s {
   int blocks_per_cu = 2;
   bool has_mat = false;
   int64_t steps = 0;
+  // batched sweep launches: per-instance scratch areas and right-hand sides,
+  // sweep arguments, workgroup maps (r: all instances; z: per chunk shape)
+  BatchLayout slay{};
+  char* saux = nullptr;
+  double* srhs = nullptr;
+  long* srhs_off = nullptr;
+  StripArgs* sargs = nullptr;
+  int* smap = nullptr;
+  int nmap_r[3] = {0, 0, 0}, rmap_off[3] = {0, 0, 0};  // r: slots of 16, 32, 64 tiles
+  int nmap_z[4] = {0, 0, 0, 0}, zmap_off[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -298,6 +309,90 @@ adi_status ensure_scratch(adi_batch b) {
   }
   ADI_TRY(dev_alloc((void**)&b->scratch, (size_t)b->lay.stride * want, b->stream));
   b->nblocks = want;
+  return ADI_OK;
+}
+
+// Buffers of the batched sweep launches (allocated on first use).
+adi_status ensure_sweep(adi_batch b) {
+  if (b->saux) return ADI_OK;
+  b->slay = make_layout(0, 0);  // scratch areas without right-hand sides
+  std::vector<long> off(b->n);
+  long total = 0;
+  std::vector<int> map;
+  for (int i = 0; i < b->n; ++i) {
+    const Params& P = b->hinst[i].P;
+    off[i] = total;
+    total += (2 * batch_strip_doubles(P.nr, P.nz) + 31) & ~31L;
+  }
+  for (int w = 0; w < 3; ++w) {
+    const int cpw = 16 << w, per = 64 / cpw;
+    b->rmap_off[w] = (int)map.size();
+    for (int i = 0; i < b->n; ++i)
+      if (bsweep_r_cpw(b->hinst[i].P.nr) == cpw)
+        for (int J = 0; J < (b->hinst[i].P.nz + 3) / 4; J += per) map.push_back(256 * i + J);
+    b->nmap_r[w] = (int)map.size() - b->rmap_off[w];
+  }
+  for (int c = 0; c < 4; ++c) {
+    b->zmap_off[c] = (int)map.size();
+    for (int i = 0; i < b->n; ++i)
+      if (b->hinst[i].zss == c)
+        for (int q = 0; q < (b->hinst[i].P.nr + 3) / 4; ++q) map.push_back(256 * i + q);
+    b->nmap_z[c] = (int)map.size() - b->zmap_off[c];
+  }
+  ADI_TRY(dev_alloc((void**)&b->saux, (size_t)b->slay.stride * b->n, b->stream));
+  ADI_TRY(dev_alloc((void**)&b->srhs, sizeof(double) * total, b->stream));
+  ADI_TRY(dev_alloc((void**)&b->srhs_off, sizeof(long) * b->n, b->stream));
+  ADI_TRY(dev_alloc((void**)&b->sargs, sizeof(StripArgs) * 3 * b->n, b->stream));
+  ADI_TRY(dev_alloc((void**)&b->smap, sizeof(int) * map.size(), b->stream));
+  ADI_HIP(hipMemcpyAsync(b->srhs_off, off.data(), sizeof(long) * b->n, hipMemcpyHostToDevice, b->stream));
+  ADI_HIP(hipMemcpyAsync(b->smap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, b->stream));
+  ADI_HIP(hipStreamSynchronize(b->stream));
+  return ADI_OK;
+}
+
+// The time loop as batched sweep launches on the batch's stream (being
+// captured by the caller): instance prologues, then per step one r launch
+// and one z launch per chunk shape, and the profile launch at snapshots.
+adi_status launch_sweeps(adi_batch b, int64_t nsteps, int snapshot_every, int nsnap, int npts) {
+  BSweepArgs a;
+  a.inst = b->dinst;
+  a.aux = b->saux;
+  a.lay = b->slay;
+  a.rhs = b->srhs;
+  a.rhs_off = b->srhs_off;
+  a.args = b->sargs;
+  a.n = b->n;
+  a.T = b->T;
+  a.prof = b->prof;
+  a.npts = npts;
+  a.map = b->smap;
+  hipLaunchKernelGGL(k_bsetup, dim3(b->n), dim3(256), 0, b->stream, a);
+  int snap = 0;
+  for (int64_t st = 1; st <= nsteps; ++st) {
+    const bool take = snapshot_every > 0 && st % snapshot_every == 0 && snap < nsnap;
+    const int write_T = (take || st == nsteps) ? 1 : 0;
+    for (int w = 0; w < 3; ++w) {
+      if (!b->nmap_r[w]) continue;
+      a.map = b->smap + b->rmap_off[w];
+      if (w == 0) hipLaunchKernelGGL(k_bsweep_r<16>, dim3(b->nmap_r[w]), dim3(64), 0, b->stream, a);
+      else if (w == 1) hipLaunchKernelGGL(k_bsweep_r<32>, dim3(b->nmap_r[w]), dim3(64), 0, b->stream, a);
+      else hipLaunchKernelGGL(k_bsweep_r<64>, dim3(b->nmap_r[w]), dim3(64), 0, b->stream, a);
+    }
+    for (int c = 0; c < 4; ++c) {
+      if (!b->nmap_z[c]) continue;
+      a.map = b->smap + b->zmap_off[c];
+      switch (c) {
+        case 0: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[0]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+        case 1: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[1]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+        case 2: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[2]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+        default: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[3]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+      }
+    }
+    if (take) {
+      hipLaunchKernelGGL(k_bprofile, dim3(b->n), dim3(64), 0, b->stream, a, snap, nsnap);
+      ++snap;
+    }
+  }
   return ADI_OK;
 }
 
@@ -459,7 +554,9 @@ adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapsh
     I.P.theta = b->scheme == ADI_PR ? 1.0 : 0.0;
   }
   ADI_HIP(hipMemcpyAsync(b->dinst, b->hinst.data(), sizeof(BatchInst) * b->n, hipMemcpyHostToDevice, b->stream));
-  ADI_TRY(ensure_scratch(b));
+  const BatchVariant& V = kBatchVariants[b->variant];
+  if (!V.fn) ADI_TRY(ensure_sweep(b));
+  else ADI_TRY(ensure_scratch(b));
   BatchArgs a;
   a.inst = b->dinst;
   a.order = b->dorder;
@@ -473,12 +570,16 @@ adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapsh
   a.nsteps = (int)nsteps;
   a.scratch = b->scratch;
   a.lay = b->lay;
-  const BatchVariant& V = kBatchVariants[b->variant];
-  // queue reset + persistent kernel, captured into one graph and launched
+  // queue reset + persistent kernel (or the batched sweep launches),
+  // captured into one graph and launched
   hipGraph_t graph = nullptr;
   ADI_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, b->stream, b->queue);
-  hipLaunchKernelGGL(V.fn, dim3(b->nblocks), dim3(64 * V.NW), 0, b->stream, a);
+  if (V.fn) {
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, b->stream, b->queue);
+    hipLaunchKernelGGL(V.fn, dim3(b->nblocks), dim3(64 * V.NW), 0, b->stream, a);
+  } else {
+    (void)launch_sweeps(b, nsteps, snapshot_every, nsnap, npts);
+  }
   hipError_t e = hipStreamEndCapture(b->stream, &graph);
   if (e != hipSuccess) return fail(ADI_EDEVICE, "capture of the batch launch: %s", hipGetErrorString(e));
   hipGraphExec_t exec = nullptr;
@@ -524,7 +625,8 @@ adi_status adi_batch_info(adi_batch b, int64_t* total_cells, int32_t* nsnap, int
   ADI_TRY(batch_handle(b));
   if (total_cells) *total_cells = b->total_cells;
   if (nsnap) *nsnap = b->nsnap;
-  if (workgroups) *workgroups = b->nblocks;
+  if (workgroups)
+    *workgroups = kBatchVariants[b->variant].fn ? b->nblocks : b->nmap_r[0] + b->nmap_r[1] + b->nmap_r[2];
   return ADI_OK;
 }
 
@@ -559,7 +661,8 @@ void adi_batch_destroy(adi_batch b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  void* bufs[] = {b->dinst, b->dorder, b->queue, b->T, b->prof, b->scratch};
+  void* bufs[] = {b->dinst, b->dorder, b->queue, b->T, b->prof, b->scratch, b->saux, b->srhs, b->srhs_off,
+                  b->sargs, b->smap};
   for (void* p : bufs) dev_free(p);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;

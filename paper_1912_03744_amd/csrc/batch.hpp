@@ -75,18 +75,140 @@ __host__ __device__ inline long batch_strip_doubles(int nr, int nz) {
   return (long)((nr + 3) / 4) * 16L * ((nz + 3) / 4);
 }
 
+// The geometry of an instance in its scratch area (fixed-size arrays).
+__device__ __forceinline__ Geom batch_geom(char* ws, const BatchLayout& Ly) {
+  Geom g;
+  double* gd = (double*)(ws + Ly.geo);
+  g.rf = gd; g.rc = gd + (kMaxNr + 1); g.dr = gd + 2 * (kMaxNr + 1);
+  g.zf = gd + 3 * (kMaxNr + 1); g.zc = g.zf + (kMaxNz + 1); g.dz = g.zf + 2 * (kMaxNz + 1);
+  g.kap = (uint8_t*)(ws + Ly.kap);
+  g.bet = (uint8_t*)(ws + Ly.bet);
+  return g;
+}
+
+// Prologue of an instance on the strip-layout batch paths, by a whole
+// workgroup: geometry and line-class tables (64 chunks per line: r lines 4
+// cells per chunk, z lines kBSZ_M[zss]) in the scratch area ws, the first
+// r half step's right-hand side (from the uniform field T0; strip layout,
+// exact zeros outside the domain and in the padding) into dA, and the sweep
+// arguments (r: dA -> dB, z: dB -> dA, no solution output), written by
+// thread 0 into ar and az.  Ends with a workgroup barrier.
+__device__ void batch_strip_prologue(const BatchInst& I, char* ws, const BatchLayout& Ly, double* dA, double* dB,
+                                     StripArgs* ar, StripArgs* az) {
+  const Params& P = I.P;
+  const int nr = P.nr, nz = P.nz;
+  const int Mz = kBSZ_M[I.zss];
+  int* ranges = (int*)(ws + Ly.ranges);
+  Geom g = batch_geom(ws, Ly);
+  build_geometry(P, nullptr, nullptr, g, ranges);
+
+  double* rpos = (double*)(ws + Ly.rpos);
+  double* rchk = (double*)(ws + Ly.rchk);
+  double* reng = (double*)(ws + Ly.reng);
+  double* rxc = (double*)(ws + Ly.rxc);
+  double* zpos = (double*)(ws + Ly.zpos);
+  double* zchk = (double*)(ws + Ly.zchk);
+  double* zeng = (double*)(ws + Ly.zeng);
+  double* zxc = (double*)(ws + Ly.zxc);
+  double* work = (double*)(ws + Ly.work);
+  const long rGM = (long)kBS_G * kBSR_M, zGM = (long)kBS_G * Mz;
+  for (int c = 0; c < 3; ++c)
+    assemble_class(P, g, 0, c, kBS_G, kBSR_M, rpos + c * P_NFIELDS * rGM, rchk + c * C_NFIELDS * kBS_G,
+                   reng + c * 2 * nr, rxc + c * nr, work);
+  for (int c = 0; c < 4; ++c)
+    assemble_class(P, g, 1, c, kBS_G, Mz, zpos + c * P_NFIELDS * zGM, zchk + c * C_NFIELDS * kBS_G,
+                   zeng + c * 2 * nz, zxc + c * nz, work);
+  // sweep arguments (uniform across the workgroup; read on use)
+  if (threadIdx.x == 0) {
+    bool ambient = false;
+    for (int c = 0; c < 4; ++c) ambient = ambient || P.tinf[c] != 0.0;
+    for (int c = 0; c < MAX_CLS; ++c) {
+      LineTab t;
+      const int cr = c < 3 ? c : 0;
+      t.pos = rpos + cr * P_NFIELDS * rGM;
+      t.chk = rchk + cr * C_NFIELDS * kBS_G;
+      t.n = nr; t.G = kBS_G; t.M = kBSR_M;
+      skip_range(0, cr, ranges, nr, &t.skip_lo, &t.skip_hi);
+      ar->tabs[c] = t;
+      t.pos = zpos + c * P_NFIELDS * zGM;
+      t.chk = zchk + c * C_NFIELDS * kBS_G;
+      t.n = nz; t.G = kBS_G; t.M = Mz;
+      skip_range(1, c, ranges, nz, &t.skip_lo, &t.skip_hi);
+      az->tabs[c] = t;
+    }
+    ar->strip = az->strip = 16L * ((nz + 3) / 4);
+    ar->nr = az->nr = nr;
+    ar->nz = az->nz = nz;
+    ar->xc = ambient ? zxc : nullptr;  // the r sweep adds b_z, the z sweep b_r
+    az->xc = ambient ? rxc : nullptr;
+    ar->nlines = nz;
+    az->nlines = nr;
+    strip_class_ends(ranges, 0, 3, ar->line_end);
+    strip_class_ends(ranges, 1, 4, ar->pos_end);
+    ar->nxcls = 4;
+    strip_class_ends(ranges, 1, 4, az->line_end);
+    strip_class_ends(ranges, 0, 3, az->pos_end);
+    az->nxcls = 3;
+    ar->nblocks = az->nblocks = 0;
+    ar->nmix = az->nmix = 0;
+    ar->theta = az->theta = P.theta;
+    ar->din = dA; ar->dout = dB; ar->xout = nullptr;
+    az->din = dB; az->dout = dA; az->xout = nullptr;
+  }
+  const long sstrip = 16L * ((nz + 3) / 4);
+
+  // right-hand side of the first r half step from the uniform field T0
+  const long nbuf = batch_strip_doubles(nr, nz);
+  for (long e = threadIdx.x; e < nbuf; e += blockDim.x) {
+    const long s = e / sstrip, rem = e - s * sstrip;
+    const int j = (int)(rem >> 2), i = (int)(4 * s + (rem & 3));
+    double o = 0.0;
+    if (i < nr && j < nz) {
+      const int kap = g.kap[i], bet = g.bet[j];
+      if (region_of(bet, kap) != MASKED) {
+        const double* pz = zpos + kap * P_NFIELDS * zGM;
+        const long ix = (long)(j % Mz) * kBS_G + j / Mz;
+        o = (pz[P_OD * zGM + ix] + pz[P_OL * zGM + ix] * (j > 0) + pz[P_OU * zGM + ix] * (j < nz - 1)) * I.T0 +
+            pz[P_OC * zGM + ix] + rxc[bet * nr + i];
+      }
+    }
+    dA[e] = o;
+  }
+  __syncthreads();
+}
+
+// Outer terminal-face profile of an instance (linear interpolation of its
+// top row at npts points r = (k + 1/2) rmax / npts), by a whole workgroup.
+__device__ void batch_profile(const Params& P, const Geom& g, const double* Ti, double* out, int npts) {
+  const int nr = P.nr, nz = P.nz;
+  const double* row = Ti + (long)(nz - 1) * nr;
+  for (int kk = threadIdx.x; kk < npts; kk += blockDim.x) {
+    const double r = (kk + 0.5) * P.rmax / npts;
+    double o;
+    if (r <= g.rc[0]) o = row[0];
+    else if (r >= g.rc[nr - 1]) o = row[nr - 1];
+    else {
+      int lo = 0, hi = nr - 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.rc[mid] <= r) lo = mid; else hi = mid;
+      }
+      o = row[lo] + (row[lo + 1] - row[lo]) * (r - g.rc[lo]) / (g.rc[lo + 1] - g.rc[lo]);
+    }
+    out[kk] = o;
+  }
+}
+
 // The persistent batch kernel on the strip-layout line solver.  Each
-// workgroup pops the next instance from the queue, builds its geometry and
-// line-class tables in its scratch, writes the first right-hand side (strip
-// layout, exact zeros outside the domain) and runs the time loop: every wave
-// takes whole blocks of 4 lines (r row groups, then z strips) and solves
-// them alone (DPP scans inside the wave, no workgroup barrier inside a
-// sweep); the workgroup synchronises between sweeps.
+// workgroup pops the next instance from the queue, runs its prologue
+// (geometry, tables, first right-hand side) in its scratch and runs the
+// time loop: every wave takes whole blocks of 4 lines (r row groups, then z
+// strips) and solves them alone (DPP scans inside the wave, no workgroup
+// barrier inside a sweep); the workgroup synchronises between sweeps.
 template <int NW>
 __global__ void __launch_bounds__(64 * NW) k_batch_s(BatchArgs a) {
   __shared__ __align__(16) double lbuf[NW][64 * 4 * 8];  // per wave: a z strip or 64 r tiles
   __shared__ double lcarry[NW][strip_carry(1)];          // unused: one wave per line
-  __shared__ LineTab s_tabs[2][MAX_CLS];
   __shared__ StripArgs s_args[2];  // r sweep, z sweep
   __shared__ int s_next;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -94,7 +216,6 @@ __global__ void __launch_bounds__(64 * NW) k_batch_s(BatchArgs a) {
   const BatchLayout& Ly = a.lay;
   double* dA = (double*)(ws + Ly.dA);
   double* dB = (double*)(ws + Ly.dB);
-  int* ranges = (int*)(ws + Ly.ranges);
   for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(a.queue, 1);
     __syncthreads();
@@ -105,99 +226,8 @@ __global__ void __launch_bounds__(64 * NW) k_batch_s(BatchArgs a) {
     const BatchInst I = a.inst[idx];
     const Params& P = I.P;
     const int nr = P.nr, nz = P.nz;
-    const int Mz = kBSZ_M[I.zss];
-
-    Geom g;
-    double* gd = (double*)(ws + Ly.geo);
-    g.rf = gd; g.rc = gd + (kMaxNr + 1); g.dr = gd + 2 * (kMaxNr + 1);
-    g.zf = gd + 3 * (kMaxNr + 1); g.zc = g.zf + (kMaxNz + 1); g.dz = g.zf + 2 * (kMaxNz + 1);
-    g.kap = (uint8_t*)(ws + Ly.kap);
-    g.bet = (uint8_t*)(ws + Ly.bet);
-    build_geometry(P, nullptr, nullptr, g, ranges);
-
-    double* rpos = (double*)(ws + Ly.rpos);
-    double* rchk = (double*)(ws + Ly.rchk);
-    double* reng = (double*)(ws + Ly.reng);
-    double* rxc = (double*)(ws + Ly.rxc);
-    double* zpos = (double*)(ws + Ly.zpos);
-    double* zchk = (double*)(ws + Ly.zchk);
-    double* zeng = (double*)(ws + Ly.zeng);
-    double* zxc = (double*)(ws + Ly.zxc);
-    double* work = (double*)(ws + Ly.work);
-    const long rGM = (long)kBS_G * kBSR_M, zGM = (long)kBS_G * Mz;
-    for (int c = 0; c < 3; ++c)
-      assemble_class(P, g, 0, c, kBS_G, kBSR_M, rpos + c * P_NFIELDS * rGM, rchk + c * C_NFIELDS * kBS_G,
-                     reng + c * 2 * nr, rxc + c * nr, work);
-    for (int c = 0; c < 4; ++c)
-      assemble_class(P, g, 1, c, kBS_G, Mz, zpos + c * P_NFIELDS * zGM, zchk + c * C_NFIELDS * kBS_G,
-                     zeng + c * 2 * nz, zxc + c * nz, work);
-    if (threadIdx.x == 0) {
-      for (int c = 0; c < MAX_CLS; ++c) {
-        LineTab t;
-        const int cr = c < 3 ? c : 0;
-        t.pos = rpos + cr * P_NFIELDS * rGM;
-        t.chk = rchk + cr * C_NFIELDS * kBS_G;
-        t.n = nr; t.G = kBS_G; t.M = kBSR_M;
-        skip_range(0, cr, ranges, nr, &t.skip_lo, &t.skip_hi);
-        s_tabs[0][c] = t;
-        t.pos = zpos + c * P_NFIELDS * zGM;
-        t.chk = zchk + c * C_NFIELDS * kBS_G;
-        t.n = nz; t.G = kBS_G; t.M = Mz;
-        skip_range(1, c, ranges, nz, &t.skip_lo, &t.skip_hi);
-        s_tabs[1][c] = t;
-      }
-    }
-    __syncthreads();
-
-    // sweep arguments, in LDS (uniform across the workgroup; read on use)
-    if (threadIdx.x == 0) {
-      bool ambient = false;
-      for (int c = 0; c < 4; ++c) ambient = ambient || P.tinf[c] != 0.0;
-      StripArgs& ar = s_args[0];
-      StripArgs& az = s_args[1];
-      ar.strip = az.strip = 16L * ((nz + 3) / 4);
-      ar.nr = az.nr = nr;
-      ar.nz = az.nz = nz;
-      for (int c = 0; c < MAX_CLS; ++c) {
-        ar.tabs[c] = s_tabs[0][c];
-        az.tabs[c] = s_tabs[1][c];
-      }
-      ar.xc = ambient ? zxc : nullptr;  // the r sweep adds b_z, the z sweep b_r
-      az.xc = ambient ? rxc : nullptr;
-      ar.nlines = nz;
-      az.nlines = nr;
-      strip_class_ends(ranges, 0, 3, ar.line_end);
-      strip_class_ends(ranges, 1, 4, ar.pos_end);
-      ar.nxcls = 4;
-      strip_class_ends(ranges, 1, 4, az.line_end);
-      strip_class_ends(ranges, 0, 3, az.pos_end);
-      az.nxcls = 3;
-      ar.nblocks = az.nblocks = 0;
-      ar.nmix = az.nmix = 0;
-      ar.theta = az.theta = P.theta;
-      ar.din = dA; ar.dout = dB; ar.xout = nullptr;
-      az.din = dB; az.dout = dA; az.xout = nullptr;
-    }
-    const long sstrip = 16L * ((nz + 3) / 4);
-
-    // right-hand side of the first r half step from the uniform field T0
-    const long nbuf = batch_strip_doubles(nr, nz);
-    for (long e = threadIdx.x; e < nbuf; e += blockDim.x) {
-      const long s = e / sstrip, rem = e - s * sstrip;
-      const int j = (int)(rem >> 2), i = (int)(4 * s + (rem & 3));
-      double o = 0.0;
-      if (i < nr && j < nz) {
-        const int kap = g.kap[i], bet = g.bet[j];
-        if (region_of(bet, kap) != MASKED) {
-          const double* pz = zpos + kap * P_NFIELDS * zGM;
-          const long ix = (long)(j % Mz) * kBS_G + j / Mz;
-          o = (pz[P_OD * zGM + ix] + pz[P_OL * zGM + ix] * (j > 0) + pz[P_OU * zGM + ix] * (j < nz - 1)) * I.T0 +
-              pz[P_OC * zGM + ix] + rxc[bet * nr + i];
-        }
-      }
-      dA[e] = o;
-    }
-    __syncthreads();
+    batch_strip_prologue(I, ws, Ly, dA, dB, &s_args[0], &s_args[1]);
+    const Geom g = batch_geom(ws, Ly);
 
     double* Ti = a.T + I.toff;
     const int nrg = (nz + 3) / 4, nstrips = (nr + 3) / 4;
@@ -217,29 +247,86 @@ __global__ void __launch_bounds__(64 * NW) k_batch_s(BatchArgs a) {
       }
       __syncthreads();
       if (take) {
-        // outer terminal-face profile from the top row
-        const double* row = Ti + (long)(nz - 1) * nr;
-        for (int kk = threadIdx.x; kk < a.npts; kk += blockDim.x) {
-          const double r = (kk + 0.5) * P.rmax / a.npts;
-          double o;
-          if (r <= g.rc[0]) o = row[0];
-          else if (r >= g.rc[nr - 1]) o = row[nr - 1];
-          else {
-            int lo = 0, hi = nr - 1;
-            while (hi - lo > 1) {
-              const int mid = (lo + hi) >> 1;
-              if (g.rc[mid] <= r) lo = mid; else hi = mid;
-            }
-            o = row[lo] + (row[lo + 1] - row[lo]) * (r - g.rc[lo]) / (g.rc[lo + 1] - g.rc[lo]);
-          }
-          a.prof[((long)idx * a.nsnap + snap) * a.npts + kk] = o;
-        }
+        batch_profile(P, g, Ti, a.prof + ((long)idx * a.nsnap + snap) * a.npts, a.npts);
         ++snap;
         __syncthreads();
       }
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------- batched sweep launches ---
+//
+// The other way to run the batch: every half step is one launch over all
+// instances (r), or over the instances of one z chunk shape (z), with one
+// single-wave workgroup per block of 4 lines.  Hundreds of thousands of
+// independent workgroups per launch keep every CU busy with workgroups in
+// different phases (loading, solving, storing), unlike the persistent
+// kernel, where each workgroup steps one instance alone.  Each instance
+// keeps its own strip-layout right-hand sides and scratch area.
+
+// Arguments of the batched-sweep kernels.
+struct BSweepArgs {
+  const BatchInst* inst;
+  char* aux;           // scratch areas, one per instance (stride lay.stride)
+  BatchLayout lay;
+  double* rhs;         // right-hand sides: instance i at rhs_off[i] (dA), + its strip size (dB)
+  const long* rhs_off;
+  StripArgs* args;     // [3][n]: r sweep, z sweep, z sweep writing the field
+  const int* map;      // workgroup -> 256 * instance + block of 4 lines
+  int n;
+  double* T;
+  double* prof;
+  int npts;
+};
+
+// One workgroup per instance: prologue into its own scratch area and
+// right-hand sides.
+__global__ void __launch_bounds__(256) k_bsetup(BSweepArgs a) {
+  const int i = blockIdx.x;
+  const BatchInst I = a.inst[i];
+  double* dA = a.rhs + a.rhs_off[i];
+  double* dB = dA + batch_strip_doubles(I.P.nr, I.P.nz);
+  batch_strip_prologue(I, a.aux + (long)i * a.lay.stride, a.lay, dA, dB, &a.args[i], &a.args[a.n + i]);
+  if (threadIdx.x == 0) {
+    a.args[2 * a.n + i] = a.args[a.n + i];
+    a.args[2 * a.n + i].xout = a.T + I.toff;
+  }
+}
+
+// r half step of the instances whose rows fit CPW tiles (4*CPW cells):
+// workgroup -> (instance, first of 64/CPW consecutive row groups).
+template <int CPW>
+__global__ void __launch_bounds__(64) k_bsweep_r(BSweepArgs a) {
+  __shared__ __align__(16) double buf[64 * 18];
+  __shared__ double carry[strip_carry(1)];
+  const int e = a.map[xcd_block(blockIdx.x, gridDim.x)];
+  strip_r_slots<CPW>(a.args[e >> 8], e & 255, buf, carry);
+}
+
+// Tile slot width of the batched r sweep of an instance with nr columns.
+__host__ __device__ inline int bsweep_r_cpw(int nr) {
+  const int tiles = (nr + 3) / 4;
+  return tiles <= 16 ? 16 : (tiles <= 32 ? 32 : 64);
+}
+
+// z half step of the instances of chunk shape M: workgroup -> (instance,
+// strip); the solution goes to the instance's field when `snap` is set.
+template <int M>
+__global__ void __launch_bounds__(64) k_bsweep_z(BSweepArgs a, int snap) {
+  __shared__ __align__(16) double buf[64 * 4 * M];
+  __shared__ double carry[strip_carry(1)];
+  const int e = a.map[xcd_block(blockIdx.x, gridDim.x)];
+  strip_z_body<M, 1>(a.args[(snap ? 2 : 1) * a.n + (e >> 8)], e & 255, threadIdx.x, buf, carry);
+}
+
+// Terminal-face profiles of every instance (snapshot `snap` of nsnap).
+__global__ void __launch_bounds__(64) k_bprofile(BSweepArgs a, int snap, int nsnap) {
+  const int i = blockIdx.x;
+  const BatchInst I = a.inst[i];
+  const Geom g = batch_geom(a.aux + (long)i * a.lay.stride, a.lay);
+  batch_profile(I.P, g, a.T + I.toff, a.prof + ((long)i * nsnap + snap) * a.npts, a.npts);
 }
 
 }  // namespace adi

@@ -866,7 +866,9 @@ __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, 
 
 // Solve a block of R lines in place.  Lane k = 64*wave + lane holds chunk
 // k (M cells) of each of the R lines in v[R][M]; the NW waves of the
-// workgroup hold the G = 64*NW chunks of the lines.  Lines r < NA have the
+// workgroup hold the G = 64*NW chunks of the lines.  With CPW < 64 (one
+// wave), each slot of CPW consecutive lanes holds its own R lines of CPW
+// chunks.  Lines r < NA have the
 // factors LA, the others LB (a block whose lines span two classes; NA = R:
 // one class, LB unused).  Same partition method as solve_group (interior
 // elimination with the class's precomputed factors, reduced system by
@@ -876,13 +878,15 @@ __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, 
 // so they solve to 0 without masking.  `lds` holds 2*NW*(R+2) doubles.
 // Every lane of the workgroup must call this (it contains barriers when
 // NW > 1).
-template <int M, int NW, int R, int NA>
+template <int M, int NW, int R, int NA, int CPW = 64>
 __device__ __forceinline__ void solve_lanes(double (*v)[M], const LaneTab<M>& LA, const LaneTab<M>& LB,
                                             double* lds) {
   static_assert(M >= 3, "chunks need an interior row");
   static_assert(NA >= 1 && NA <= R, "split");
+  static_assert(NW == 1 || CPW == 64, "lines narrower than a wave stay inside it");
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
+  const int ci = lane & (CPW - 1);  // chunk within the lane's slot of CPW lanes
 #define ADI_TAB(r) ((r) < NA ? LA : LB)
 
   // interior forward elimination and back substitution (rows 1..M-2)
@@ -915,7 +919,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], const LaneTab<M>& LA
     F[r] = (v[r][M - 1] - L.ae * v[r][M - 2]) * L.W1 - L.Q1 * g0w[r];
   }
   double BA = LA.Q1 * LA.Q0, BB = LB.Q1 * LB.Q0;
-  slot_scan_fwd<64, R, NA>(F, BA, BB);
+  slot_scan_fwd<CPW, R, NA>(F, BA, BB);
   double Fin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Fin[r] = 0.0;
@@ -940,7 +944,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], const LaneTab<M>& LA
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     Fprev[r] = __shfl_up(F[r], 1, 64);
-    if (lane == 0) Fprev[r] = Fin[r];
+    if (ci == 0) Fprev[r] = Fin[r];
   }
 
   // backward recurrence
@@ -948,7 +952,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], const LaneTab<M>& LA
 #pragma unroll
   for (int r = 0; r < R; ++r) U[r] = g0w[r] - ADI_TAB(r).Q0 * Fprev[r] - ADI_TAB(r).C0 * F[r];
   double EA = LA.C0 * LA.C1, EB = LB.C0 * LB.C1;
-  slot_scan_bwd<64, R, NA>(U, EA, EB);
+  slot_scan_bwd<CPW, R, NA>(U, EA, EB);
   double Uin[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Uin[r] = 0.0;
@@ -974,7 +978,7 @@ __device__ __forceinline__ void solve_lanes(double (*v)[M], const LaneTab<M>& LA
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     double un = __shfl_down(U[r], 1, 64);
-    if (lane == 63) un = Uin[r];
+    if (ci == CPW - 1) un = Uin[r];
     const double xs = U[r];
     const double xe = F[r] - ADI_TAB(r).C1 * un;
     v[r][0] = xs;

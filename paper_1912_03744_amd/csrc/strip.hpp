@@ -312,13 +312,12 @@ __device__ __forceinline__ void strip_z_body(const StripArgs& a, int s, int tid,
   const int nact = min(4, a.nr - c0);
   const int c_lo = class_at(a.line_end, c0), c_hi = class_at(a.line_end, c0 + nact - 1);
   stage_z<M>(a, s, tid, buf);
-  LaneTab<M> L;  // behind the data loads
-  load_lanetab<M, NT>(L, a.tabs[c_lo].pos, a.tabs[c_lo].chk, tid);
   wave_sync();
   double* mine_slots = buf + tid * 4 * M;
   zero_past_edge<M>(mine_slots, nact);
   for (int c = c_lo; c <= c_hi; ++c) {
-    if (c > c_lo) load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
+    LaneTab<M> L;  // behind the data loads; live for one pass only
+    load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
     z_pass<M, NW, 4>(a, c0, tid, mine_slots, L, L, carry, false, block_lines_of(a, c0, nact, c));
   }
   wave_sync();
@@ -384,8 +383,6 @@ __device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid,
   const int nact = min(4, a.nz - j0);
   const int p0 = tid * M;
   const int c_lo = class_at(a.line_end, j0), c_hi = class_at(a.line_end, j0 + nact - 1);
-  LaneTab<M> L;
-  load_lanetab<M, NT>(L, a.tabs[c_lo].pos, a.tabs[c_lo].chk, tid);
   const int nstrips = (a.nr + 3) >> 2;
   const int lane = tid & 63, wst0 = (tid >> 6) * 64;
 #pragma unroll
@@ -406,7 +403,8 @@ __device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid,
     }
   auto rhs = [&](int r, int t) { return mine_slots[r * 4 + t]; };
   for (int c = c_lo; c <= c_hi; ++c) {
-    if (c > c_lo) load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
+    LaneTab<M> L;  // behind the data loads; live for one pass only
+    load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
     const unsigned mask = block_lines_of(a, j0, nact, c);
     double v[4][M];
 #pragma unroll
@@ -442,6 +440,75 @@ __device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid,
     if (st < nstrips)
       *(double2*)(a.dout + (long)st * a.strip + (long)j0 * 4 + (q & 7) * 2) =
           *(const double2*)&buf[st * CH + (q & 7) * 2];
+  }
+}
+
+// The r-sweep work of one wave on 64/CPW consecutive row groups J0, J0+1,
+// ... (lines of up to 4*CPW cells): lane slot g = lane / CPW holds row
+// group J0 + g, lane ci = lane % CPW of the slot holds tile ci of it, in its
+// own LDS slots (buf: 64*18 doubles).  Rows of each band present are solved
+// in one pass per band (each slot emits only its rows of that band).  Used
+// by the batched sweep launches, where lines are short and the solution of
+// an r half step is not written out.
+template <int CPW>
+__device__ __forceinline__ void strip_r_slots(const StripArgs& a, int J0, double* buf, double* carry) {
+  constexpr int M = 4;
+  constexpr int CH = 18;  // a 16-double tile + 2 pad
+  constexpr int S = 64 / CPW;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / CPW, ci = lane % CPW;
+  const int nrg = (a.nz + 3) >> 2, nstrips = (a.nr + 3) >> 2;
+  const int j0 = 4 * (J0 + g);  // first row of the lane's row group
+  const int nact = max(0, min(4, a.nz - j0));
+  const int row_lo = 4 * J0, row_hi = min(4 * (J0 + S), a.nz) - 1;
+  const int c_lo = class_at(a.line_end, row_lo), c_hi = class_at(a.line_end, row_hi);
+  // data: tile t = q/8 of the wave (slot t / CPW, tile t % CPW), piece q%8
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = lane + u * 64;
+    const int t = q >> 3, tg = t / CPW, tk = t % CPW;
+    double2 x = make_double2(0.0, 0.0);
+    if (tk < nstrips && J0 + tg < nrg)
+      x = *(const double2*)(a.din + (long)tk * a.strip + (long)(J0 + tg) * 16 + (q & 7) * 2);
+    *(double2*)&buf[t * CH + (q & 7) * 2] = x;
+  }
+  wave_sync();
+  double* mine_slots = buf + lane * CH;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r >= nact) {
+      *(double2*)&mine_slots[r * 4] = make_double2(0.0, 0.0);
+      *(double2*)&mine_slots[r * 4 + 2] = make_double2(0.0, 0.0);
+    }
+  for (int c = c_lo; c <= c_hi; ++c) {
+    LaneTab<M> L;  // behind the data loads; live for one pass only
+    load_lanetab<M, 64>(L, a.tabs[c].pos, a.tabs[c].chk, ci);
+    const unsigned mask = block_lines_of(a, j0, nact, c);
+    double v[4][M];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double2 lo = *(const double2*)&mine_slots[r * 4];
+      const double2 hi = *(const double2*)&mine_slots[r * 4 + 2];
+      v[r][0] = lo.x; v[r][1] = lo.y; v[r][2] = hi.x; v[r][3] = hi.y;
+    }
+    solve_lanes<M, 1, 4, 4, CPW>(v, L, L, carry);
+    block_outputs<M, 4>(a, v, L, L, mask, [&](int r, int t) { return mine_slots[r * 4 + t]; });
+    if (a.xc) add_crossing<M>(a, v, j0, mask, a.nr, ci * M);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if ((mask >> r) & 1u) {
+        *(double2*)&mine_slots[r * 4] = make_double2(v[r][0], v[r][1]);
+        *(double2*)&mine_slots[r * 4 + 2] = make_double2(v[r][2], v[r][3]);
+      }
+  }
+  wave_sync();
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = lane + u * 64;
+    const int t = q >> 3, tg = t / CPW, tk = t % CPW;
+    if (tk < nstrips && J0 + tg < nrg)
+      *(double2*)(a.dout + (long)tk * a.strip + (long)(J0 + tg) * 16 + (q & 7) * 2) =
+          *(const double2*)&buf[t * CH + (q & 7) * 2];
   }
 }
 

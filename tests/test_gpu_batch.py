@@ -18,7 +18,7 @@ def _oracle_run(s, nsteps):
     return P, T
 
 
-@pytest.mark.parametrize("shape", [None, (4, 4, 2)], ids=["default", "strips"])
+@pytest.mark.parametrize("shape", [None, (4, 4, 2), (4, 1, 1)], ids=["default", "strips", "sweeps"])
 @pytest.mark.parametrize("scheme", ["pr", "lod"])
 def test_batch_instances_match_oracle(scheme, shape):
     """A stratified ragged batch (every size class, seeded designs) after 60
@@ -56,7 +56,7 @@ def test_batch_odd_sizes_and_launch_shapes():
     sizes = [(3, 3), (5, 7), (64, 160), (65, 161), (97, 241), (129, 321), (191, 479), (192, 480), (33, 400)]
     specs = [s.replace(nr=sizes[i % len(sizes)][0], nz=sizes[i % len(sizes)][1]) for i, s in enumerate(base)]
     want = [_oracle_run(s, 15) for s in specs]
-    for shape in ((1, 4, 1), (2, 4, 2), (1, 8, 1), (2, 8, 1), (4, 4, 2), (4, 8, 1)):
+    for shape in ((1, 4, 1), (2, 4, 2), (1, 8, 1), (2, 8, 1), (4, 4, 2), (4, 8, 1), (4, 1, 1)):
         b = native.Batch(specs)
         b.set_launch(*shape)
         b.step(1e-3, 15)
