@@ -225,8 +225,9 @@ static BatchLayout make_layout(long maxcells, long maxstrip) {
   };
   // tables sized for both kernel families (rows layout, strip layout)
   const long rGM = std::max((long)kBR_G * kBR_M[3], (long)kBS_G * kBSR_M);
-  const long zGM = std::max((long)kBZ_G * kBZ_M[3], (long)kBS_G * kBSZ_M[3]);
-  const long rG = std::max(kBR_G, kBS_G), zG = std::max(kBZ_G, kBS_G);
+  long zGM = std::max((long)kBZ_G * kBZ_M[3], (long)kBS_G * kBSZ_M[3]);
+  for (int c = 0; c < 4; ++c) zGM = std::max(zGM, (long)kBWZ_G[c] * kBWZ_M[c]);
+  const long rG = std::max(kBR_G, kBS_G), zG = std::max(std::max(kBZ_G, kBS_G), kBWZ_G[3]);
   L.dA = put(8 * std::max(maxcells, maxstrip));
   L.dB = put(8 * std::max(maxcells, maxstrip));
   L.geo = put(8 * (3 * (kMaxNr + 1) + 3 * (kMaxNz + 1)));
@@ -243,8 +244,10 @@ static BatchLayout make_layout(long maxcells, long maxstrip) {
   L.zchk = put(8 * 4 * C_NFIELDS * zG);
   L.zeng = put(8 * 4 * 2 * kMaxNz);
   L.zxc = put(8 * 4 * kMaxNz);
-  L.work = put(8 * std::max(std::max(assemble_work(kBR_G, kBR_M[3]), assemble_work(kBZ_G, kBZ_M[3])),
-                            std::max(assemble_work(kBS_G, kBSR_M), assemble_work(kBS_G, kBSZ_M[3]))));
+  long work = std::max(std::max(assemble_work(kBR_G, kBR_M[3]), assemble_work(kBZ_G, kBZ_M[3])),
+                       std::max(assemble_work(kBS_G, kBSR_M), assemble_work(kBS_G, kBSZ_M[3])));
+  for (int c = 0; c < 4; ++c) work = std::max(work, assemble_work(kBWZ_G[c], kBWZ_M[c]));
+  L.work = put(8 * work);
   L.stride = off;
   return L;
 }
@@ -381,11 +384,12 @@ adi_status launch_sweeps(adi_batch b, int64_t nsteps, int snapshot_every, int ns
     for (int c = 0; c < 4; ++c) {
       if (!b->nmap_z[c]) continue;
       a.map = b->smap + b->zmap_off[c];
+      constexpr int W3 = kBWZ_G[3] / 64;
       switch (c) {
-        case 0: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[0]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
-        case 1: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[1]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
-        case 2: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[2]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
-        default: hipLaunchKernelGGL(k_bsweep_z<kBSZ_M[3]>, dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+        case 0: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[0], 1>), dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+        case 1: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[1], 1>), dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+        case 2: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[2], 1>), dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
+        default: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[3], W3>), dim3(b->nmap_z[c]), dim3(64 * W3), 0, b->stream, a, write_T); break;
       }
     }
     if (take) {

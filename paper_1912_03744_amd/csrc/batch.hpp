@@ -63,6 +63,10 @@ __device__ __forceinline__ void skip_range(int dir, int cls, const int* ranges, 
 constexpr int kBSR_M = 4;
 constexpr int kBSZ_M[4] = {3, 4, 5, 8};
 constexpr int kBS_G = 64;
+// z lines of the batched sweep launches: chunks (64 per wave) and cells per
+// chunk of each z shape (the longest lines on two waves of 4-cell chunks)
+constexpr int kBWZ_G[4] = {64, 64, 64, 128};
+constexpr int kBWZ_M[4] = {3, 4, 5, 4};
 
 __host__ __device__ inline int batch_strip_zshape(int nz) {
   for (int s = 0; s < 4; ++s)
@@ -87,17 +91,16 @@ __device__ __forceinline__ Geom batch_geom(char* ws, const BatchLayout& Ly) {
 }
 
 // Prologue of an instance on the strip-layout batch paths, by a whole
-// workgroup: geometry and line-class tables (64 chunks per line: r lines 4
-// cells per chunk, z lines kBSZ_M[zss]) in the scratch area ws, the first
+// workgroup: geometry and line-class tables (r lines 64 chunks of 4 cells,
+// z lines Gz chunks of Mz cells) in the scratch area ws, the first
 // r half step's right-hand side (from the uniform field T0; strip layout,
 // exact zeros outside the domain and in the padding) into dA, and the sweep
 // arguments (r: dA -> dB, z: dB -> dA, no solution output), written by
 // thread 0 into ar and az.  Ends with a workgroup barrier.
 __device__ void batch_strip_prologue(const BatchInst& I, char* ws, const BatchLayout& Ly, double* dA, double* dB,
-                                     StripArgs* ar, StripArgs* az) {
+                                     StripArgs* ar, StripArgs* az, int Gz, int Mz) {
   const Params& P = I.P;
   const int nr = P.nr, nz = P.nz;
-  const int Mz = kBSZ_M[I.zss];
   int* ranges = (int*)(ws + Ly.ranges);
   Geom g = batch_geom(ws, Ly);
   build_geometry(P, nullptr, nullptr, g, ranges);
@@ -111,12 +114,12 @@ __device__ void batch_strip_prologue(const BatchInst& I, char* ws, const BatchLa
   double* zeng = (double*)(ws + Ly.zeng);
   double* zxc = (double*)(ws + Ly.zxc);
   double* work = (double*)(ws + Ly.work);
-  const long rGM = (long)kBS_G * kBSR_M, zGM = (long)kBS_G * Mz;
+  const long rGM = (long)kBS_G * kBSR_M, zGM = (long)Gz * Mz;
   for (int c = 0; c < 3; ++c)
     assemble_class(P, g, 0, c, kBS_G, kBSR_M, rpos + c * P_NFIELDS * rGM, rchk + c * C_NFIELDS * kBS_G,
                    reng + c * 2 * nr, rxc + c * nr, work);
   for (int c = 0; c < 4; ++c)
-    assemble_class(P, g, 1, c, kBS_G, Mz, zpos + c * P_NFIELDS * zGM, zchk + c * C_NFIELDS * kBS_G,
+    assemble_class(P, g, 1, c, Gz, Mz, zpos + c * P_NFIELDS * zGM, zchk + c * C_NFIELDS * Gz,
                    zeng + c * 2 * nz, zxc + c * nz, work);
   // sweep arguments (uniform across the workgroup; read on use)
   if (threadIdx.x == 0) {
@@ -131,8 +134,8 @@ __device__ void batch_strip_prologue(const BatchInst& I, char* ws, const BatchLa
       skip_range(0, cr, ranges, nr, &t.skip_lo, &t.skip_hi);
       ar->tabs[c] = t;
       t.pos = zpos + c * P_NFIELDS * zGM;
-      t.chk = zchk + c * C_NFIELDS * kBS_G;
-      t.n = nz; t.G = kBS_G; t.M = Mz;
+      t.chk = zchk + c * C_NFIELDS * Gz;
+      t.n = nz; t.G = Gz; t.M = Mz;
       skip_range(1, c, ranges, nz, &t.skip_lo, &t.skip_hi);
       az->tabs[c] = t;
     }
@@ -167,7 +170,7 @@ __device__ void batch_strip_prologue(const BatchInst& I, char* ws, const BatchLa
       const int kap = g.kap[i], bet = g.bet[j];
       if (region_of(bet, kap) != MASKED) {
         const double* pz = zpos + kap * P_NFIELDS * zGM;
-        const long ix = (long)(j % Mz) * kBS_G + j / Mz;
+        const long ix = (long)(j % Mz) * Gz + j / Mz;
         o = (pz[P_OD * zGM + ix] + pz[P_OL * zGM + ix] * (j > 0) + pz[P_OU * zGM + ix] * (j < nz - 1)) * I.T0 +
             pz[P_OC * zGM + ix] + rxc[bet * nr + i];
       }
@@ -226,7 +229,7 @@ __global__ void __launch_bounds__(64 * NW) k_batch_s(BatchArgs a) {
     const BatchInst I = a.inst[idx];
     const Params& P = I.P;
     const int nr = P.nr, nz = P.nz;
-    batch_strip_prologue(I, ws, Ly, dA, dB, &s_args[0], &s_args[1]);
+    batch_strip_prologue(I, ws, Ly, dA, dB, &s_args[0], &s_args[1], kBS_G, kBSZ_M[I.zss]);
     const Geom g = batch_geom(ws, Ly);
 
     double* Ti = a.T + I.toff;
@@ -288,7 +291,8 @@ __global__ void __launch_bounds__(256) k_bsetup(BSweepArgs a) {
   const BatchInst I = a.inst[i];
   double* dA = a.rhs + a.rhs_off[i];
   double* dB = dA + batch_strip_doubles(I.P.nr, I.P.nz);
-  batch_strip_prologue(I, a.aux + (long)i * a.lay.stride, a.lay, dA, dB, &a.args[i], &a.args[a.n + i]);
+  batch_strip_prologue(I, a.aux + (long)i * a.lay.stride, a.lay, dA, dB, &a.args[i], &a.args[a.n + i],
+                       kBWZ_G[I.zss], kBWZ_M[I.zss]);
   if (threadIdx.x == 0) {
     a.args[2 * a.n + i] = a.args[a.n + i];
     a.args[2 * a.n + i].xout = a.T + I.toff;
@@ -311,14 +315,15 @@ __host__ __device__ inline int bsweep_r_cpw(int nr) {
   return tiles <= 16 ? 16 : (tiles <= 32 ? 32 : 64);
 }
 
-// z half step of the instances of chunk shape M: workgroup -> (instance,
-// strip); the solution goes to the instance's field when `snap` is set.
-template <int M>
-__global__ void __launch_bounds__(64) k_bsweep_z(BSweepArgs a, int snap) {
-  __shared__ __align__(16) double buf[64 * 4 * M];
-  __shared__ double carry[strip_carry(1)];
+// z half step of the instances of one z shape (NW waves of chunks of M
+// cells): workgroup -> (instance, strip); the solution goes to the
+// instance's field when `snap` is set.
+template <int M, int NW>
+__global__ void __launch_bounds__(64 * NW) k_bsweep_z(BSweepArgs a, int snap) {
+  __shared__ __align__(16) double buf[64 * NW * 4 * M];
+  __shared__ double carry[strip_carry(NW)];
   const int e = a.map[xcd_block(blockIdx.x, gridDim.x)];
-  strip_z_body<M, 1>(a.args[(snap ? 2 : 1) * a.n + (e >> 8)], e & 255, threadIdx.x, buf, carry);
+  strip_z_body<M, NW>(a.args[(snap ? 2 : 1) * a.n + (e >> 8)], e & 255, threadIdx.x, buf, carry);
 }
 
 // Terminal-face profiles of every instance (snapshot `snap` of nsnap).
