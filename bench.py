@@ -21,8 +21,9 @@ Prints one JSON line:
               (latency-bound; microseconds per step)
   batch       secondary figure: the ragged design batch (4096 seeded
               instances of 64x160 ... 192x480 cells, 2000 PR steps of 1e-3)
-              in one persistent launch, autotuned; cell-updates/s and the
-              kernel's algorithmic bandwidth (32 B per active cell per step)
+              in one captured graph: a persistent kernel or batched sweep
+              launches, whichever the autotuner picks; cell-updates/s and the
+              algorithmic bandwidth (32 B per active cell per step)
 Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 200] [--no-batch]
        python bench.py --counter-workload          (the program profiled for traffic)
        python bench.py --summarize-counters DIR    (rocprofv3 --pmc output -> profiles/)
@@ -83,7 +84,7 @@ def cpu_baseline(spec, steps):
                       % (steps, spec.nr, spec.nz), "seconds": round(dt, 3)}
 
 
-def batch_leg(n, steps, tune=True):
+def batch_leg(n, steps, tune=True, shape=(2, 8, 1)):
     """The ragged design batch: one timed adi_batch_step call over all
     instances from their initial fields (events on the batch's stream)."""
     from paper_1912_03744_amd import autotune, native
@@ -94,19 +95,24 @@ def batch_leg(n, steps, tune=True):
     if tune:
         t0 = time.perf_counter()
         tuned = autotune.apply_batch(b, dt, "pr")
+        shape = tuple(tuned["shape"])
         print("bench: batch autotune %.1f s -> %s" % (time.perf_counter() - t0, tuned["shape"]),
               file=sys.stderr, flush=True)
+    else:
+        b.set_launch(*shape)
+    mode = ("batched sweep launches (one per half step and line shape) in one graph" if shape[1] == 1
+            else "one persistent launch")
     b.time(dt, 20, 1)  # warm-up (allocates the workgroup scratch)
     ms = b.time(dt, steps, 1)
     active, cells = b.active_cells(), b.cells()
     sec = ms * 1e-3
     achieved = 2 * BYTES_PER_CELL_HALF_STEP * active * steps / sec / 1e9
-    shape = b.info()
+    info = b.info()
     out = {"workload": "ragged design batch: %d instances, sizes U{64x160, 96x240, 128x320, 192x480}, "
-                       "master seed 0, Peaceman-Rachford, dt=%g, %d steps, one persistent launch" % (n, dt, steps),
+                       "master seed 0, Peaceman-Rachford, dt=%g, %d steps, %s" % (n, dt, steps, mode),
            "value": active * steps / sec, "unit": "cell-updates/s", "cups_all_cells": cells * steps / sec,
            "seconds": sec, "designs_per_s": n / sec, "active_cells": active, "cells": cells,
-           "workgroups": shape["workgroups"],
+           "launch": list(shape), "workgroups": info["workgroups"],
            "roofline": {"bound": "hbm", "kernel": "batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
     b.close()
@@ -233,6 +239,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-only", metavar="R,NW,BPC", default=None,
+                    help="run only the batch, in this launch shape (no autotuning), and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -246,6 +254,10 @@ def main():
     from paper_1912_03744_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.batch_only:
+        shape = tuple(int(x) for x in args.batch_only.split(","))
+        print(json.dumps(batch_leg(args.batch_n, args.batch_steps, tune=False, shape=shape)), flush=True)
+        return
     spec = W.production(args.seed)
     p = native.Problem.from_spec(spec)
     # launch shapes: the project autotuner (times every compiled shape once,

@@ -79,9 +79,10 @@ def in_box(D: np.ndarray) -> np.ndarray:
 
 
 def solve_profiles(D: np.ndarray, nsteps=2000, dt=1e-3, snap_every=100, grid=LABEL_GRID, chunk=4096,
-                   log=None, launch=(2, 8, 1)):
+                   log=None, launch=(4, 1, 1)):
     """Terminal-face profiles of designs D (rows of 11 parameters) from the
-    batched FP64 solver: [n, nsteps // snap_every, 64]."""
+    batched FP64 solver (by default as batched sweep launches): [n,
+    nsteps // snap_every, 64]."""
     n = len(D)
     nsnap = nsteps // snap_every if snap_every else 0
     out = np.empty((n, max(nsnap, 1), NPTS))
