@@ -215,42 +215,6 @@ static int shape_index(const int* cover_m, int G, int n) {
   return -1;
 }
 
-static BatchLayout make_layout(long maxcells, long maxstrip) {
-  BatchLayout L{};
-  long off = 0;
-  auto put = [&](long bytes) {
-    const long o = off;
-    off += (bytes + 255) & ~255L;
-    return o;
-  };
-  // tables sized for both kernel families (rows layout, strip layout)
-  const long rGM = std::max((long)kBR_G * kBR_M[3], (long)kBS_G * kBSR_M);
-  long zGM = std::max((long)kBZ_G * kBZ_M[3], (long)kBS_G * kBSZ_M[3]);
-  for (int c = 0; c < 4; ++c) zGM = std::max(zGM, (long)kBWZ_G[c] * kBWZ_M[c]);
-  const long rG = std::max(kBR_G, kBS_G), zG = std::max(std::max(kBZ_G, kBS_G), kBWZ_G[3]);
-  L.dA = put(8 * std::max(maxcells, maxstrip));
-  L.dB = put(8 * std::max(maxcells, maxstrip));
-  L.geo = put(8 * (3 * (kMaxNr + 1) + 3 * (kMaxNz + 1)));
-  L.kap = put(kMaxNr);
-  L.bet = put(kMaxNz);
-  L.ranges = put(4 * 17);
-  L.rtabs = put(sizeof(LineTab) * 3);
-  L.rpos = put(8 * 3 * P_NFIELDS * rGM);
-  L.rchk = put(8 * 3 * C_NFIELDS * rG);
-  L.reng = put(8 * 3 * 2 * kMaxNr);
-  L.rxc = put(8 * 3 * kMaxNr);
-  L.ztabs = put(sizeof(LineTab) * 4);
-  L.zpos = put(8 * 4 * P_NFIELDS * zGM);
-  L.zchk = put(8 * 4 * C_NFIELDS * zG);
-  L.zeng = put(8 * 4 * 2 * kMaxNz);
-  L.zxc = put(8 * 4 * kMaxNz);
-  long work = std::max(std::max(assemble_work(kBR_G, kBR_M[3]), assemble_work(kBZ_G, kBZ_M[3])),
-                       std::max(assemble_work(kBS_G, kBSR_M), assemble_work(kBS_G, kBSZ_M[3])));
-  for (int c = 0; c < 4; ++c) work = std::max(work, assemble_work(kBWZ_G[c], kBWZ_M[c]));
-  L.work = put(8 * work);
-  L.stride = off;
-  return L;
-}
 
 }  // namespace adi
 
@@ -318,30 +282,13 @@ adi_status ensure_scratch(adi_batch b) {
 // Buffers of the batched sweep launches (allocated on first use).
 adi_status ensure_sweep(adi_batch b) {
   if (b->saux) return ADI_OK;
-  b->slay = make_layout(0, 0);  // scratch areas without right-hand sides
-  std::vector<long> off(b->n);
-  long total = 0;
-  std::vector<int> map;
-  for (int i = 0; i < b->n; ++i) {
-    const Params& P = b->hinst[i].P;
-    off[i] = total;
-    total += (2 * batch_strip_doubles(P.nr, P.nz) + 31) & ~31L;
-  }
-  for (int w = 0; w < 3; ++w) {
-    const int cpw = 16 << w, per = 64 / cpw;
-    b->rmap_off[w] = (int)map.size();
-    for (int i = 0; i < b->n; ++i)
-      if (bsweep_r_cpw(b->hinst[i].P.nr) == cpw)
-        for (int J = 0; J < (b->hinst[i].P.nz + 3) / 4; J += per) map.push_back(256 * i + J);
-    b->nmap_r[w] = (int)map.size() - b->rmap_off[w];
-  }
-  for (int c = 0; c < 4; ++c) {
-    b->zmap_off[c] = (int)map.size();
-    for (int i = 0; i < b->n; ++i)
-      if (b->hinst[i].zss == c)
-        for (int q = 0; q < (b->hinst[i].P.nr + 3) / 4; ++q) map.push_back(256 * i + q);
-    b->nmap_z[c] = (int)map.size() - b->zmap_off[c];
-  }
+  b->slay = batch_layout(0, 0);  // scratch areas without right-hand sides
+  const BSweepPlan plan = bsweep_plan(b->hinst.data(), b->n);
+  const std::vector<long>& off = plan.off;
+  const std::vector<int>& map = plan.map;
+  const long total = plan.total;
+  for (int w = 0; w < 3; ++w) b->nmap_r[w] = plan.nmap_r[w], b->rmap_off[w] = plan.rmap_off[w];
+  for (int c = 0; c < 4; ++c) b->nmap_z[c] = plan.nmap_z[c], b->zmap_off[c] = plan.zmap_off[c];
   ADI_TRY(dev_alloc((void**)&b->saux, (size_t)b->slay.stride * b->n, b->stream));
   ADI_TRY(dev_alloc((void**)&b->srhs, sizeof(double) * total, b->stream));
   ADI_TRY(dev_alloc((void**)&b->srhs_off, sizeof(long) * b->n, b->stream));
@@ -464,7 +411,7 @@ adi_status adi_create_batch(int32_t n, const adi_geometry* geoms, const adi_bc* 
     b->active += (long)g.nr * g.nz - ncol * nrow;
   }
   b->total_cells = off;
-  b->lay = make_layout(b->maxcells, b->maxstrip);
+  b->lay = batch_layout(b->maxcells, b->maxstrip);
   hipError_t e = hipGetDevice(&b->device);
   if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
   b->stream = (hipStream_t)hip_stream;

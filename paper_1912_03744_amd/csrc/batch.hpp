@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "device.hpp"
 #include "strip.hpp"
 
@@ -332,6 +335,82 @@ __global__ void __launch_bounds__(64) k_bprofile(BSweepArgs a, int snap, int nsn
   const BatchInst I = a.inst[i];
   const Geom g = batch_geom(a.aux + (long)i * a.lay.stride, a.lay);
   batch_profile(I.P, g, a.T + I.toff, a.prof + ((long)i * nsnap + snap) * a.npts, a.npts);
+}
+
+// Scratch layout of one workgroup (persistent kernels) or one instance
+// (batched sweeps, maxcells = maxstrip = 0: no right-hand sides).
+inline BatchLayout batch_layout(long maxcells, long maxstrip) {
+  BatchLayout L{};
+  long off = 0;
+  auto put = [&](long bytes) {
+    const long o = off;
+    off += (bytes + 255) & ~255L;
+    return o;
+  };
+  // tables sized for both kernel families (rows layout, strip layout)
+  const long rGM = std::max((long)kBR_G * kBR_M[3], (long)kBS_G * kBSR_M);
+  long zGM = std::max((long)kBZ_G * kBZ_M[3], (long)kBS_G * kBSZ_M[3]);
+  for (int c = 0; c < 4; ++c) zGM = std::max(zGM, (long)kBWZ_G[c] * kBWZ_M[c]);
+  const long rG = std::max(kBR_G, kBS_G), zG = std::max(std::max(kBZ_G, kBS_G), kBWZ_G[3]);
+  L.dA = put(8 * std::max(maxcells, maxstrip));
+  L.dB = put(8 * std::max(maxcells, maxstrip));
+  L.geo = put(8 * (3 * (kMaxNr + 1) + 3 * (kMaxNz + 1)));
+  L.kap = put(kMaxNr);
+  L.bet = put(kMaxNz);
+  L.ranges = put(4 * 17);
+  L.rtabs = put(sizeof(LineTab) * 3);
+  L.rpos = put(8 * 3 * P_NFIELDS * rGM);
+  L.rchk = put(8 * 3 * C_NFIELDS * rG);
+  L.reng = put(8 * 3 * 2 * kMaxNr);
+  L.rxc = put(8 * 3 * kMaxNr);
+  L.ztabs = put(sizeof(LineTab) * 4);
+  L.zpos = put(8 * 4 * P_NFIELDS * zGM);
+  L.zchk = put(8 * 4 * C_NFIELDS * zG);
+  L.zeng = put(8 * 4 * 2 * kMaxNz);
+  L.zxc = put(8 * 4 * kMaxNz);
+  long work = std::max(std::max(assemble_work(kBR_G, kBR_M[3]), assemble_work(kBZ_G, kBZ_M[3])),
+                       std::max(assemble_work(kBS_G, kBSR_M), assemble_work(kBS_G, kBSZ_M[3])));
+  for (int c = 0; c < 4; ++c) work = std::max(work, assemble_work(kBWZ_G[c], kBWZ_M[c]));
+  L.work = put(8 * work);
+  L.stride = off;
+  return L;
+}
+
+// Host plan of the batched sweep launches: each instance's right-hand sides
+// (two strip-layout buffers, 256-byte aligned) in one arena, and the
+// workgroup maps (256 * instance + first block of 4 lines): r launches by
+// row slot width (16, 32, 64 tiles), z launches by z shape.
+struct BSweepPlan {
+  std::vector<long> off;  // doubles
+  long total = 0;
+  std::vector<int> map;
+  int nmap_r[3] = {0, 0, 0}, rmap_off[3] = {0, 0, 0};
+  int nmap_z[4] = {0, 0, 0, 0}, zmap_off[4] = {0, 0, 0, 0};
+};
+
+inline BSweepPlan bsweep_plan(const BatchInst* inst, int n) {
+  BSweepPlan p;
+  p.off.resize(n);
+  for (int i = 0; i < n; ++i) {
+    p.off[i] = p.total;
+    p.total += (2 * batch_strip_doubles(inst[i].P.nr, inst[i].P.nz) + 31) & ~31L;
+  }
+  for (int w = 0; w < 3; ++w) {
+    const int cpw = 16 << w, per = 64 / cpw;
+    p.rmap_off[w] = (int)p.map.size();
+    for (int i = 0; i < n; ++i)
+      if (bsweep_r_cpw(inst[i].P.nr) == cpw)
+        for (int J = 0; J < (inst[i].P.nz + 3) / 4; J += per) p.map.push_back(256 * i + J);
+    p.nmap_r[w] = (int)p.map.size() - p.rmap_off[w];
+  }
+  for (int c = 0; c < 4; ++c) {
+    p.zmap_off[c] = (int)p.map.size();
+    for (int i = 0; i < n; ++i)
+      if (inst[i].zss == c)
+        for (int q = 0; q < (inst[i].P.nr + 3) / 4; ++q) p.map.push_back(256 * i + q);
+    p.nmap_z[c] = (int)p.map.size() - p.zmap_off[c];
+  }
+  return p;
 }
 
 }  // namespace adi

@@ -327,6 +327,9 @@ class Batch:
     __del__ = close
 
     def set_launch(self, lines_per_lane, waves_per_block, blocks_per_cu):
+        """(1|2, 4|8, bpc): persistent kernel on the rows layout; (4, 4|8,
+        bpc): persistent kernel on the strip layout; (4, 1, 1): batched
+        sweep launches (one launch per half step over all instances)."""
         check(lib().adi_batch_set_launch(self._h, int(lines_per_lane), int(waves_per_block),
                                          int(blocks_per_cu)))
 
