@@ -253,7 +253,8 @@ adi_status adi_batch_read_profiles(adi_batch b, double* host_out, size_t count);
 adi_status adi_batch_read_field(adi_batch b, int32_t i, double* host_out, size_t count);
 
 /* Total cells over all instances, snapshots per instance of the last step,
- * persistent workgroups launched. */
+ * workgroups: persistent workgroups launched, or the r-sweep workgroups of
+ * one step for the batched sweep launches. */
 adi_status adi_batch_info(adi_batch b, int64_t* total_cells, int32_t* nsnap, int32_t* workgroups);
 
 /* Cells inside the domain (not masked) summed over all instances. */
