@@ -44,11 +44,17 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_HALF_STEP = 16
 
 
+# The sources the production sweeps are built and launched from: the counter
+# readings stay valid while these are unchanged.
+SWEEP_SOURCES = ("common.hpp", "device.hpp", "strip.hpp", "solver.hip")
+
+
 def source_digest():
-    """Hash of the HIP sources, to tie stored counter readings to a build."""
+    """Hash of the HIP sources of the production sweeps, to tie stored
+    counter readings to a build."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1912_03744_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in SWEEP_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
