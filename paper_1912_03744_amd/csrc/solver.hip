@@ -840,7 +840,7 @@ adi_status adi_create_problem(const adi_geometry* g, const adi_bc* bc, adi_schem
   // field and work buffers
   // dA, dB and mid also hold the strip layout: ceil(nr/4) strips, each of
   // 4*ceil(nz/4) rows of 4 doubles
-  p->strip = 4L * (4L * ((nz + 3) / 4));
+  p->strip = strip_stride(nz);
   const long nbuf = std::max(n, (long)((nr + 3) / 4) * p->strip);
   double** bufs[] = {&p->T, &p->dA, &p->dB, &p->mid};
   for (double** b : bufs)

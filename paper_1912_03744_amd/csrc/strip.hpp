@@ -25,13 +25,19 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 // Alternative storage of the carried right-hand sides for coalesced sweeps
 // in both directions: the columns are grouped in strips of 4, each strip is
 // one contiguous array of rows of 4 doubles (element (j, i) at
-// (i/4)*strip + 4*j + i%4, with strip = 16*ceil(nz/4) doubles: 4*ceil(nz/4)
-// rows).  A z sweep then
+// (i/4)*strip + 4*j + i%4, with strip = strip_stride(nz) doubles: at least
+// 4*ceil(nz/4) rows).  A z sweep then
 // reads and writes one contiguous block per strip; an r sweep over 4
 // consecutive rows touches one whole 128-byte tile per strip.  Both kernels
 // stage their block through LDS with fully coalesced copies, and each lane
 // solves the same chunk of 4 lines, so every table value it loads serves
 // 4 lines.
+
+// Doubles per strip: 4*ceil(nz/4) rows of 4 plus 1 KB, so that the tiles
+// an r sweep reads from consecutive strips (one strip apart) do not all fall
+// on the same memory channels when the rows alone span a power of two.
+// Padding rows hold 0 and are never read by a sweep.
+__host__ __device__ inline long strip_stride(int nz) { return 16L * ((nz + 3) / 4) + 128; }
 
 struct StripArgs {
   const double* din;        // right-hand side of this half step (strip layout)

@@ -64,7 +64,7 @@ int run(Params P, double dt, int nsteps, int scheme, double T0, const char* out)
     }
     for (int c = X.ncls; c < MAX_CLS; ++c) X.tabs[c] = X.tabs[0];
   }
-  const long strip = 16L * ((nz + 3) / 4);
+  const long strip = strip_stride(nz);
   const long nbuf = (long)((nr + 3) / 4) * strip;
   std::vector<double> T((long)nr * nz, 0.0), dA(nbuf, 0.0), dB(nbuf, 0.0);
   for (int j = 0; j < nz; ++j)
