@@ -236,9 +236,9 @@ adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t wav
  * (each call starts again from the initial fields), recording the outer
  * terminal-face profile (top row resampled at r_k = (k+0.5)*rmax/npts, as in
  * adi_read_profile) after every snapshot_every-th step (0 = none).  Enqueued
- * on the batch's stream as one captured HIP graph (queue reset + persistent
- * kernel, or the instance set-up and every sweep launch of the nsteps
- * steps); returns without waiting. */
+ * on the batch's stream as captured HIP graphs: one for the persistent
+ * kernel (queue reset + kernel), or, for the batched sweep launches, one per
+ * 256 steps (the instance set-up in the first); returns without waiting. */
 adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapshot_every, int32_t npts);
 
 /* Wait for the batch's stream. */

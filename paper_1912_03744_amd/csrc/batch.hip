@@ -300,10 +300,13 @@ adi_status ensure_sweep(adi_batch b) {
   return ADI_OK;
 }
 
-// The time loop as batched sweep launches on the batch's stream (being
-// captured by the caller): instance prologues, then per step one r launch
-// and one z launch per chunk shape, and the profile launch at snapshots.
-adi_status launch_sweeps(adi_batch b, int64_t nsteps, int snapshot_every, int nsnap, int npts) {
+// Steps st0 .. st1 (1-based, inclusive) of the time loop as batched sweep
+// launches on the batch's stream (being captured by the caller): the
+// instance prologues first when st0 is 1, then per step one r launch per row
+// slot width and one z launch per z shape (the last of the nsteps steps and
+// snapshot steps write the field), and the profile launch at snapshots.
+void launch_sweeps(adi_batch b, int64_t st0, int64_t st1, int64_t nsteps, int snapshot_every, int nsnap,
+                   int npts) {
   BSweepArgs a;
   a.inst = b->dinst;
   a.aux = b->saux;
@@ -316,9 +319,9 @@ adi_status launch_sweeps(adi_batch b, int64_t nsteps, int snapshot_every, int ns
   a.prof = b->prof;
   a.npts = npts;
   a.map = b->smap;
-  hipLaunchKernelGGL(k_bsetup, dim3(b->n), dim3(256), 0, b->stream, a);
-  int snap = 0;
-  for (int64_t st = 1; st <= nsteps; ++st) {
+  if (st0 == 1) hipLaunchKernelGGL(k_bsetup, dim3(b->n), dim3(256), 0, b->stream, a);
+  for (int64_t st = st0; st <= st1; ++st) {
+    const int64_t snap = snapshot_every > 0 ? st / snapshot_every - 1 : -1;  // index if st is a snapshot step
     const bool take = snapshot_every > 0 && st % snapshot_every == 0 && snap < nsnap;
     const int write_T = (take || st == nsteps) ? 1 : 0;
     for (int w = 0; w < 3; ++w) {
@@ -339,13 +342,32 @@ adi_status launch_sweeps(adi_batch b, int64_t nsteps, int snapshot_every, int ns
         default: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[3], W3>), dim3(b->nmap_z[c]), dim3(64 * W3), 0, b->stream, a, write_T); break;
       }
     }
-    if (take) {
-      hipLaunchKernelGGL(k_bprofile, dim3(b->n), dim3(64), 0, b->stream, a, snap, nsnap);
-      ++snap;
-    }
+    if (take) hipLaunchKernelGGL(k_bprofile, dim3(b->n), dim3(64), 0, b->stream, a, (int)snap, nsnap);
   }
+}
+
+// Capture whatever `enqueue` puts on the batch's stream into a graph and
+// launch it (the graph is released once it has run).
+template <class F>
+adi_status launch_captured(adi_batch b, F enqueue) {
+  hipGraph_t graph = nullptr;
+  ADI_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  enqueue();
+  hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  if (e != hipSuccess) return fail(ADI_EDEVICE, "capture of the batch launch: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ADI_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  e = hipGraphLaunch(exec, b->stream);
+  (void)hipGraphExecDestroy(exec);
+  if (e != hipSuccess) return fail(ADI_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
   return ADI_OK;
 }
+
+// Steps per captured graph of the batched sweep launches (about 8 launches
+// per step): bounds the graph's size for any number of steps.
+constexpr int64_t kSweepGraphSteps = 256;
 
 }  // namespace
 
@@ -521,25 +543,19 @@ adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapsh
   a.nsteps = (int)nsteps;
   a.scratch = b->scratch;
   a.lay = b->lay;
-  // queue reset + persistent kernel (or the batched sweep launches),
-  // captured into one graph and launched
-  hipGraph_t graph = nullptr;
-  ADI_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   if (V.fn) {
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, b->stream, b->queue);
-    hipLaunchKernelGGL(V.fn, dim3(b->nblocks), dim3(64 * V.NW), 0, b->stream, a);
+    // queue reset + persistent kernel, captured into one graph and launched
+    ADI_TRY(launch_captured(b, [&] {
+      hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, b->stream, b->queue);
+      hipLaunchKernelGGL(V.fn, dim3(b->nblocks), dim3(64 * V.NW), 0, b->stream, a);
+    }));
   } else {
-    (void)launch_sweeps(b, nsteps, snapshot_every, nsnap, npts);
+    // batched sweep launches, captured kSweepGraphSteps steps at a time
+    for (int64_t st0 = 1; st0 <= nsteps; st0 += kSweepGraphSteps) {
+      const int64_t st1 = std::min(nsteps, st0 + kSweepGraphSteps - 1);
+      ADI_TRY(launch_captured(b, [&] { launch_sweeps(b, st0, st1, nsteps, snapshot_every, nsnap, npts); }));
+    }
   }
-  hipError_t e = hipStreamEndCapture(b->stream, &graph);
-  if (e != hipSuccess) return fail(ADI_EDEVICE, "capture of the batch launch: %s", hipGetErrorString(e));
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return fail(ADI_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-  e = hipGraphLaunch(exec, b->stream);
-  (void)hipGraphExecDestroy(exec);
-  if (e != hipSuccess) return fail(ADI_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
   b->steps = nsteps;
   return ADI_OK;
 }

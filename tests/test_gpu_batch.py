@@ -132,3 +132,24 @@ def test_batch_full_size_sampled(tmp_path, monkeypatch):
         assert rel_inf(b.field(i), want, P.active()) <= TOL, (i, s.nr, s.nz)
         wp = P.profile(want, 0, 64)
         assert np.max(np.abs(prof[i, 1] - wp)) <= TOL * np.max(np.abs(wp))
+
+
+def test_batch_sweeps_across_graph_segments():
+    """Batched sweep launches over more steps than one captured graph holds
+    (256): snapshots in the first and second graph and the final field
+    against the oracle."""
+    from paper_1912_03744_amd import native
+    specs = W.ragged_batch(6, master_seed=21, scheme="pr", dt=1e-3, nsteps=300)
+    b = native.Batch(specs, scheme="pr")
+    b.set_launch(4, 1, 1)
+    b.step(1e-3, 300, snapshot_every=100, npts=64)
+    prof = b.profiles()
+    assert prof.shape == (6, 3, 64)
+    for i, s in enumerate(specs):
+        P = oracle.Problem.from_spec(s)
+        T = P.initial(s.T0)
+        for k in range(3):
+            T, _ = P.step(T, "pr", 1e-3, 100)
+            wp = P.profile(T, 0, 64)
+            assert np.max(np.abs(prof[i, k] - wp)) <= TOL * np.max(np.abs(wp)), (i, k)
+        assert rel_inf(b.field(i), T, P.active()) <= TOL, i
