@@ -182,6 +182,24 @@ def test_production_energy_identity_long_run():
     assert np.nanmin(got) >= 0.0
 
 
+def test_production_benchmark_configuration(tmp_path, monkeypatch):
+    """The benchmark's run itself (seed 0, Peaceman-Rachford, dt = 1e-4,
+    10,000 steps, graphs of 100 steps, energy identity checked on the device
+    every 100 steps, autotuned layout and shapes): all 100 checks pass with
+    a residual at rounding level and the field stays finite.  (Parity of
+    the same shapes against the oracle: the full-size short run.)"""
+    from paper_1912_03744_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
+    s = W.production(0)
+    _say("production benchmark configuration, 10000 steps")
+    p, got = run_gpu(s, 10_000, graph_steps=100, check_every=100, tune=True)
+    e = p.energy()
+    assert e["checks"] == 100
+    assert e["residual"] < 1e-12
+    act = ~np.isnan(got)
+    assert np.all(np.isfinite(got[act]))
+
+
 def test_graph_and_checks_do_not_change_results():
     s = W.production(1, nr=200, nz=500)
     _say("graph vs plain")
