@@ -21,7 +21,7 @@ Prints one JSON line:
               (latency-bound; microseconds per step)
   batch       secondary figure: the ragged design batch (4096 seeded
               instances of 64x160 ... 192x480 cells, 2000 PR steps of 1e-3)
-              in one captured graph: a persistent kernel or batched sweep
+              as captured graphs: a persistent kernel or batched sweep
               launches, whichever the autotuner picks; cell-updates/s and the
               algorithmic bandwidth (32 B per active cell per step)
 Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 200] [--no-batch]
@@ -106,8 +106,8 @@ def batch_leg(n, steps, tune=True, shape=(2, 8, 1)):
               file=sys.stderr, flush=True)
     else:
         b.set_launch(*shape)
-    mode = ("batched sweep launches (one per half step and line shape) in one graph" if shape[1] == 1
-            else "one persistent launch")
+    mode = ("batched sweep launches (one per half step and line shape), captured 256 steps per graph"
+            if shape[1] == 1 else "one persistent launch")
     b.time(dt, 20, 1)  # warm-up (allocates the workgroup scratch)
     ms = b.time(dt, steps, 1)
     active, cells = b.active_cells(), b.cells()
