@@ -12,9 +12,10 @@
  *  - Fields are double, row-major with r fastest: cell (i, j) of an nr x nz
  *    grid is element j*nr + i.  Region ids: 0 cooler, 1 inner insulator,
  *    2 heater, 3 outer insulator, 4 terminal, 255 outside the domain.
- *  - The library owns every device buffer it allocates (hipMalloc) and frees
- *    it in the matching destroy call.  Host buffers belong to the caller and
- *    are only read or written during the call.
+ *  - The library owns every device buffer it allocates (hipMalloc, or the
+ *    caller's allocator set with adi_set_allocator) and frees it in the
+ *    matching destroy call.  Host buffers belong to the caller and are only
+ *    read or written during the call.
  *  - Work is enqueued on the HIP stream given at creation; NULL makes the
  *    handle create (and later destroy) a non-blocking stream of its own, so
  *    that its steps can be captured into HIP graphs.  Calls that return host
@@ -314,6 +315,21 @@ adi_status adi_mlp_train_step(adi_mlp m, const float* dev_x, const float* dev_t,
 void adi_mlp_destroy(adi_mlp m);
 
 /* ---------------------------------------------------------- utilities -- */
+
+/* Device-memory hook (for a caller's caching allocator, e.g. PyTorch's):
+ * alloc(bytes, ctx) returns a device pointer aligned to 256 bytes, or NULL
+ * when out of memory (the calling entry point then fails with ADI_ENOMEM);
+ * free_fn(ptr, ctx) takes back a block alloc returned.  From this call on,
+ * every device allocation of the library (problems, batches, networks) goes
+ * through the hook; both NULL restores hipMalloc / hipFree.  Each block is
+ * returned to the free function that was set when it was allocated, after
+ * the device has finished every queued use of it (the library synchronises
+ * the device first, as hipFree does).  Process-wide; the hook functions may
+ * be called from any thread that calls the library.  Errors: ADI_EINVAL if
+ * exactly one of alloc, free_fn is NULL. */
+typedef void* (*adi_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*adi_free_fn)(void* ptr, void* ctx);
+adi_status adi_set_allocator(adi_alloc_fn alloc, adi_free_fn free_fn, void* ctx);
 
 const char* adi_status_string(adi_status s);
 const char* adi_last_error(void);

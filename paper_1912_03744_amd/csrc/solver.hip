@@ -15,6 +15,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <unordered_map>
+#include <mutex>
 
 #include "common.hpp"
 #include "device.hpp"
@@ -35,22 +37,81 @@ void set_error(const char* fmt, ...) {
   g_error = buf;
 }
 
+// Device allocations: hipMalloc / hipFree, or the caller's allocator
+// (adi_set_allocator).  Every block from the caller's allocator is recorded
+// with the free function that owns it, so a later change of allocator still
+// returns it to the right one.
+namespace {
+struct HookOwner {
+  adi_free_fn free_fn;
+  void* ctx;
+};
+std::mutex g_alloc_mu;
+adi_alloc_fn g_alloc_fn = nullptr;
+adi_free_fn g_free_fn = nullptr;
+void* g_alloc_ctx = nullptr;
+std::unordered_map<void*, HookOwner>& hooked_blocks() {
+  static std::unordered_map<void*, HookOwner> m;
+  return m;
+}
+}  // namespace
+
 adi_status dev_alloc(void** p, size_t bytes, hipStream_t stream) {
   *p = nullptr;
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return fail(e == hipErrorOutOfMemory ? ADI_ENOMEM : ADI_EDEVICE, "hipMalloc(%zu) failed: %s",
-                bytes, hipGetErrorString(e));
+  adi_alloc_fn al;
+  adi_free_fn fr;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    al = g_alloc_fn;
+    fr = g_free_fn;
+    ctx = g_alloc_ctx;
   }
-  e = hipMemsetAsync(*p, 0, bytes, stream);
+  if (al) {
+    void* q = al(bytes, ctx);
+    if (!q) return fail(ADI_ENOMEM, "allocator hook returned no memory for %zu bytes", bytes);
+    if ((uintptr_t)q % 256 != 0) {
+      fr(q, ctx);
+      return fail(ADI_EINVAL, "allocator hook returned a block not aligned to 256 bytes");
+    }
+    {
+      std::lock_guard<std::mutex> g(g_alloc_mu);
+      hooked_blocks()[q] = {fr, ctx};
+    }
+    *p = q;
+  } else {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return fail(e == hipErrorOutOfMemory ? ADI_ENOMEM : ADI_EDEVICE, "hipMalloc(%zu) failed: %s",
+                  bytes, hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipMemsetAsync(*p, 0, bytes, stream);
   if (e != hipSuccess) return fail(ADI_EDEVICE, "hipMemsetAsync failed: %s", hipGetErrorString(e));
   return ADI_OK;
 }
 
 void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  HookOwner o{nullptr, nullptr};
+  {
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    auto it = hooked_blocks().find(p);
+    if (it != hooked_blocks().end()) {
+      o = it->second;
+      hooked_blocks().erase(it);
+    }
+  }
+  if (o.free_fn) {
+    // like hipFree: no work of the library still uses the block when the
+    // caller's allocator gets it back
+    (void)hipDeviceSynchronize();
+    o.free_fn(p, o.ctx);
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 // ------------------------------------------------------------ kernels ----
@@ -779,6 +840,16 @@ const char* adi_status_string(adi_status s) {
 }
 
 const char* adi_last_error(void) { return g_error.c_str(); }
+
+adi_status adi_set_allocator(adi_alloc_fn alloc, adi_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(ADI_EINVAL, "allocator and free function must both be given or both be null");
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  g_alloc_fn = alloc;
+  g_free_fn = free_fn;
+  g_alloc_ctx = ctx;
+  return ADI_OK;
+}
 
 const char* adi_version(void) { return "adi-mi355x 0.1 (gfx950)"; }
 

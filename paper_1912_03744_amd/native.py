@@ -62,7 +62,12 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p
 
 # name -> argtypes (restype adi_status = int unless listed otherwise)
+# device-memory hook of adi_set_allocator
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _SIGS = {
+    "adi_set_allocator": [ALLOC_FN, FREE_FN, ctypes.c_void_p],
     "adi_create_problem": [ctypes.POINTER(Geometry), ctypes.POINTER(BC), ctypes.c_int, _vp,
                            ctypes.POINTER(_vp)],
     "adi_set_materials": [_vp, _dp, _dp],
@@ -117,6 +122,7 @@ _RESTYPE = {"adi_destroy": None, "adi_batch_destroy": None, "adi_mlp_destroy": N
             "adi_last_error": ctypes.c_char_p, "adi_version": ctypes.c_char_p}
 
 _LIB = None
+_HOOKS = []  # every installed allocator callback: blocks keep their free function
 
 
 def lib():
@@ -132,6 +138,29 @@ def lib():
             f.restype = _RESTYPE.get(name, ctypes.c_int)
         _LIB = L
     return _LIB
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through alloc(nbytes) -> device
+    pointer (int; 0 when out of memory) and free(ptr) (adi_set_allocator);
+    set_allocator() restores hipMalloc / hipFree.  Blocks allocated under a
+    hook go back to that hook's free function whenever they are released."""
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        check(lib().adi_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+    a = ALLOC_FN(lambda nbytes, ctx: int(alloc(int(nbytes))) or None)
+    f = FREE_FN(lambda ptr, ctx: free(int(ptr)))
+    _HOOKS.append((a, f))
+    check(lib().adi_set_allocator(a, f, None))
+
+
+def use_torch_allocator():
+    """Take the library's device memory from PyTorch's caching allocator
+    (blocks on the current device, tied to torch's current stream)."""
+    import torch
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n), torch.cuda.caching_allocator_delete)
 
 
 def exported_symbols():

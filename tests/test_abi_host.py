@@ -80,3 +80,15 @@ def test_invalid_bc_and_handles(native):
     assert lib.adi_step(None, 1e-3, 1) == native.ADI_EINVAL
     assert lib.adi_set_sources(None, None) == native.ADI_EINVAL
     lib.adi_destroy(None)
+
+
+def test_allocator_hook_arguments(native):
+    """adi_set_allocator takes both functions or neither (no device call)."""
+    lib = native.lib()
+    assert lib.adi_set_allocator(native.ALLOC_FN(), native.FREE_FN(), None) == 0
+    bad = native.ALLOC_FN(lambda n, ctx: 0)
+    assert lib.adi_set_allocator(bad, native.FREE_FN(), None) == -1
+    assert b"both" in lib.adi_last_error()
+    with pytest.raises(ValueError):
+        native.set_allocator(alloc=lambda n: 0)
+    native.set_allocator()  # back to hipMalloc / hipFree
