@@ -42,7 +42,7 @@ typedef enum {
   ADI_ESTATE = -4,       /* call not allowed in the handle's current state */
   ADI_ENONFINITE = -5,   /* a NaN/Inf appeared in the field or an input */
   ADI_EBALANCE = -6,     /* the discrete energy identity was violated */
-  ADI_EUNSUPPORTED = -7  /* combination not supported by this build */
+  ADI_EUNSUPPORTED = -7  /* combination the compiled library does not support */
 } adi_status;
 
 /* Time integrator.
@@ -176,7 +176,7 @@ adi_status adi_set_launch(adi_problem p, int32_t dir, int32_t chunk, int32_t lin
 adi_status adi_get_launch(adi_problem p, int32_t dir, int32_t* chunk, int32_t* lines_per_wave,
                           int32_t* waves_per_line, int32_t* lines_per_lane, int32_t* groups_per_block);
 
-/* Launch shapes compiled into this build for the rows layout: writes up to
+/* Launch shapes compiled into the library for the rows layout: writes up to
  * max_shapes records (chunk, lines_per_wave, waves_per_line, lines_per_lane,
  * groups_per_block) to out (5*max_shapes int32) and the number of shapes to
  * *count. */
