@@ -16,7 +16,8 @@ Prints one JSON line:
               its mean launch time, measured with HIP events on the stream
               the kernel runs on
   cpu_baseline  the CPU FP64 oracle timed on a bounded sample of the same
-              workload on this host
+              workload on this host's cores (its line solves shared among
+              OpenMP threads, as in the paper; single-threaded figure beside)
   single_layout  secondary figure: the 64x160 layout of Fig. 1, 1000 steps
               (latency-bound; microseconds per step)
   batch       secondary figure: the ragged design batch (4096 seeded
@@ -75,7 +76,22 @@ def stored_traffic(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(spec, steps):
+def host_threads():
+    """Threads for the CPU baseline: the host's share (OMP_NUM_THREADS when
+    set), at most the cores the process sees."""
+    n = os.cpu_count() or 1
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def cpu_baseline(spec, steps, threaded_steps):
+    """The oracle on a bounded sample of the workload: PR steps of the same
+    grid from T0, single-threaded and with the line solves of each half step
+    shared among the host's threads (the paper's OpenMP parallelisation; the
+    same result bit for bit).  The threaded figure is the baseline."""
     import numpy as np
 
     import oracle
@@ -84,10 +100,46 @@ def cpu_baseline(spec, steps):
     active = int(np.count_nonzero(P.active()))
     t0 = time.perf_counter()
     P.step(T, spec.scheme, spec.dt, steps)
-    dt = time.perf_counter() - t0
-    return {"value": active * steps / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d PR steps of the %dx%d grid from T0 (single-threaded C, -O2)"
-                      % (steps, spec.nr, spec.nz), "seconds": round(dt, 3)}
+    dt1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, used = P.step_threads(T, spec.scheme, spec.dt, threaded_steps, host_threads())
+    dtn = time.perf_counter() - t0
+    return {"value": active * threaded_steps / dtn, "unit": "cell-updates/s", "cores": used, "kind": "oracle",
+            "sample": "%d PR steps of the %dx%d grid from T0, C -O2, line solves of each half step on %d "
+                      "OpenMP threads" % (threaded_steps, spec.nr, spec.nz, used),
+            "seconds": round(dtn, 3),
+            "single_thread": {"value": active * steps / dt1, "cores": 1, "steps": steps,
+                              "seconds": round(dt1, 3)}}
+
+
+def batch_cpu_baseline(steps):
+    """The oracle on 16 instances of the design batch (4 per size class, the
+    batch's own generator), each stepped alone with the host's threads over
+    the lines of a half step; extrapolated per cell-update."""
+    import numpy as np
+
+    import oracle
+    from paper_1912_03744_amd import workloads as W
+    specs = W.ragged_batch(64, master_seed=0, scheme="pr", dt=1e-3, nsteps=steps)
+    picked, per = [], {}
+    for s in specs:
+        if per.get((s.nr, s.nz), 0) < 4:
+            per[(s.nr, s.nz)] = per.get((s.nr, s.nz), 0) + 1
+            picked.append(s)
+    updates, sec, used = 0, 0.0, 1
+    for s in picked:
+        P = oracle.Problem.from_spec(s)
+        T = P.initial(s.T0)
+        t0 = time.perf_counter()
+        _, used = P.step_threads(T, s.scheme, s.dt, steps, host_threads())
+        sec += time.perf_counter() - t0
+        updates += int(np.count_nonzero(P.active())) * steps
+    return {"value": updates / sec, "unit": "cell-updates/s", "cores": used, "kind": "oracle",
+            "sample": "%d instances of the batch (%s), %d PR steps each, %d OpenMP threads over the lines "
+                      "of each half step; extrapolated per cell-update"
+                      % (len(picked), ", ".join("%d of %dx%d" % (c, a, b) for (a, b), c in sorted(per.items())),
+                         steps, used),
+            "seconds": round(sec, 3)}
 
 
 def batch_leg(n, steps, tune=True, shape=(2, 8, 1)):
@@ -240,6 +292,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-threaded-steps", type=int, default=100)
+    ap.add_argument("--cpu-batch-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -336,7 +390,9 @@ def main():
         print("bench: batch %.3f s, %.3e cell-updates/s" % (out["batch"]["seconds"], out["batch"]["value"]),
               file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps, args.cpu_threaded_steps)
+        if "batch" in out:
+            out["batch"]["cpu_baseline"] = batch_cpu_baseline(args.cpu_batch_steps)
     print(json.dumps(out), flush=True)
 
 

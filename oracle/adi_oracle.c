@@ -9,8 +9,9 @@
  * HIP implementation.
  *
  * Everything is double precision, written as plain loops in the order of the
- * paper's definitions, single-threaded, and meant to be compiled with
- * -O2 -ffp-contract=off.  It is slow on purpose: every cell carries its own
+ * paper's definitions and meant to be compiled with -O2 -ffp-contract=off.
+ * The reference path (or_step) is single-threaded; or_step_omp runs the same
+ * line solves on several cores, the paper's parallelisation, for timing.  It is slow on purpose: every cell carries its own
  * operator coefficients, assembled straight from the finite-volume form, and
  * every line is solved by the Thomas algorithm without pivoting (Sec. 3, the
  * closing sentence on the solution of the line systems).
@@ -53,6 +54,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MASKED 255
 
@@ -337,28 +341,26 @@ static void lines_free(or_lines *w) {
  *   (C/ta - L_r) Tout = (C/ta) Tin + theta*(A_z Tin) + Q + b_r
  * one Thomas solve per row j.
  */
-static void half_r(const or_problem *p, double ta, double theta,
-                   const double *Tin, double *Tout, or_lines *w) {
+static void row_r(const or_problem *p, double ta, double theta,
+                  const double *Tin, double *Tout, or_lines *w, int j) {
   int nr = p->nr, nz = p->nz;
-  for (int j = 0; j < nz; ++j) {
-    for (int i = 0; i < nr; ++i) {
-      size_t c = (size_t)j * nr + i;
-      if (p->region[c] == OR_MASKED) {
-        w->a[i] = 0.0; w->b[i] = 1.0; w->c[i] = 0.0; w->d[i] = 0.0;
-        continue;
-      }
-      double Cc = p->C[c] / ta;
-      w->a[i] = -p->Lr_w[c];
-      w->b[i] = Cc - p->Lr_c[c];
-      w->c[i] = -p->Lr_e[c];
-      double az = p->Lz_c[c] * Tin[c] + p->bz[c];
-      if (j > 0) az += p->Lz_s[c] * Tin[c - nr];
-      if (j < nz - 1) az += p->Lz_n[c] * Tin[c + nr];
-      w->d[i] = Cc * Tin[c] + theta * az + p->Q[c] + p->br[c];
+  for (int i = 0; i < nr; ++i) {
+    size_t c = (size_t)j * nr + i;
+    if (p->region[c] == OR_MASKED) {
+      w->a[i] = 0.0; w->b[i] = 1.0; w->c[i] = 0.0; w->d[i] = 0.0;
+      continue;
     }
-    or_thomas(nr, w->a, w->b, w->c, w->d, w->x, w->cp, w->dp);
-    for (int i = 0; i < nr; ++i) Tout[(size_t)j * nr + i] = w->x[i];
+    double Cc = p->C[c] / ta;
+    w->a[i] = -p->Lr_w[c];
+    w->b[i] = Cc - p->Lr_c[c];
+    w->c[i] = -p->Lr_e[c];
+    double az = p->Lz_c[c] * Tin[c] + p->bz[c];
+    if (j > 0) az += p->Lz_s[c] * Tin[c - nr];
+    if (j < nz - 1) az += p->Lz_n[c] * Tin[c + nr];
+    w->d[i] = Cc * Tin[c] + theta * az + p->Q[c] + p->br[c];
   }
+  or_thomas(nr, w->a, w->b, w->c, w->d, w->x, w->cp, w->dp);
+  for (int i = 0; i < nr; ++i) Tout[(size_t)j * nr + i] = w->x[i];
 }
 
 /*
@@ -366,28 +368,26 @@ static void half_r(const or_problem *p, double ta, double theta,
  *   (C/ta - L_z) Tout = (C/ta) Tin + theta*(A_r Tin + Q) + b_z
  * one Thomas solve per column i.
  */
-static void half_z(const or_problem *p, double ta, double theta,
-                   const double *Tin, double *Tout, or_lines *w) {
+static void col_z(const or_problem *p, double ta, double theta,
+                  const double *Tin, double *Tout, or_lines *w, int i) {
   int nr = p->nr, nz = p->nz;
-  for (int i = 0; i < nr; ++i) {
-    for (int j = 0; j < nz; ++j) {
-      size_t c = (size_t)j * nr + i;
-      if (p->region[c] == OR_MASKED) {
-        w->a[j] = 0.0; w->b[j] = 1.0; w->c[j] = 0.0; w->d[j] = 0.0;
-        continue;
-      }
-      double Cc = p->C[c] / ta;
-      w->a[j] = -p->Lz_s[c];
-      w->b[j] = Cc - p->Lz_c[c];
-      w->c[j] = -p->Lz_n[c];
-      double ar = p->Lr_c[c] * Tin[c] + p->br[c];
-      if (i > 0) ar += p->Lr_w[c] * Tin[c - 1];
-      if (i < nr - 1) ar += p->Lr_e[c] * Tin[c + 1];
-      w->d[j] = Cc * Tin[c] + theta * (ar + p->Q[c]) + p->bz[c];
+  for (int j = 0; j < nz; ++j) {
+    size_t c = (size_t)j * nr + i;
+    if (p->region[c] == OR_MASKED) {
+      w->a[j] = 0.0; w->b[j] = 1.0; w->c[j] = 0.0; w->d[j] = 0.0;
+      continue;
     }
-    or_thomas(nz, w->a, w->b, w->c, w->d, w->x, w->cp, w->dp);
-    for (int j = 0; j < nz; ++j) Tout[(size_t)j * nr + i] = w->x[j];
+    double Cc = p->C[c] / ta;
+    w->a[j] = -p->Lz_s[c];
+    w->b[j] = Cc - p->Lz_c[c];
+    w->c[j] = -p->Lz_n[c];
+    double ar = p->Lr_c[c] * Tin[c] + p->br[c];
+    if (i > 0) ar += p->Lr_w[c] * Tin[c - 1];
+    if (i < nr - 1) ar += p->Lr_e[c] * Tin[c + 1];
+    w->d[j] = Cc * Tin[c] + theta * (ar + p->Q[c]) + p->bz[c];
   }
+  or_thomas(nz, w->a, w->b, w->c, w->d, w->x, w->cp, w->dp);
+  for (int j = 0; j < nz; ++j) Tout[(size_t)j * nr + i] = w->x[j];
 }
 
 /*
@@ -407,12 +407,61 @@ int or_step(const or_problem *p, int scheme, double dt, long nsteps, double *T,
   double *mid = malloc(sizeof(double) * n);
   if (!mid || !lines_alloc(&w, L)) { free(mid); lines_free(&w); return OR_ENOMEM; }
   for (long s = 0; s < nsteps; ++s) {
-    half_r(p, ta, theta, T, mid, &w);
-    half_z(p, ta, theta, mid, T, &w);
+    for (int j = 0; j < p->nz; ++j) row_r(p, ta, theta, T, mid, &w, j);
+    for (int i = 0; i < p->nr; ++i) col_z(p, ta, theta, mid, T, &w, i);
   }
   if (Tbar && nsteps > 0) memcpy(Tbar, mid, sizeof(double) * n);
   free(mid);
   lines_free(&w);
+  return OR_OK;
+}
+
+/*
+ * The same steps with the line solves of each half step shared among
+ * nthreads OpenMP threads, the parallelisation of the paper (Sec. 4: the
+ * independent line systems of a half step run on the cores of one shared-
+ * memory node).  Every line is solved by the same sequence of operations as
+ * in or_step, so T comes out bit-identical; only the CPU timing of the method
+ * changes.  *used receives the number of threads that ran.
+ */
+int or_step_omp(const or_problem *p, int scheme, double dt, long nsteps, double *T,
+                int nthreads, int *used) {
+  if (!(dt > 0.0) || nsteps < 0 || (scheme != 0 && scheme != 1) || nthreads < 1)
+    return OR_EINVAL;
+  size_t n = (size_t)p->nr * p->nz;
+  int L = p->nr > p->nz ? p->nr : p->nz;
+  double ta = scheme == 0 ? 0.5 * dt : dt;
+  double theta = scheme == 0 ? 1.0 : 0.0;
+  double *mid = malloc(sizeof(double) * n);
+  or_lines *w = calloc((size_t)nthreads, sizeof(or_lines));
+  int ok = mid && w;
+  for (int t = 0; ok && t < nthreads; ++t) ok = lines_alloc(&w[t], L);
+  if (!ok) {
+    for (int t = 0; w && t < nthreads; ++t) lines_free(&w[t]);
+    free(w); free(mid);
+    return OR_ENOMEM;
+  }
+  int ran = 1;
+#pragma omp parallel num_threads(nthreads)
+  {
+#ifdef _OPENMP
+    or_lines *mine = &w[omp_get_thread_num()];
+#pragma omp single
+    ran = omp_get_num_threads();
+#else
+    or_lines *mine = &w[0];
+#endif
+    for (long s = 0; s < nsteps; ++s) {
+#pragma omp for schedule(static)
+      for (int j = 0; j < p->nz; ++j) row_r(p, ta, theta, T, mid, mine, j);
+#pragma omp for schedule(static)
+      for (int i = 0; i < p->nr; ++i) col_z(p, ta, theta, mid, T, mine, i);
+    }
+  }
+  if (used) *used = ran;
+  for (int t = 0; t < nthreads; ++t) lines_free(&w[t]);
+  free(w);
+  free(mid);
   return OR_OK;
 }
 

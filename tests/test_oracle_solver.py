@@ -414,3 +414,20 @@ def test_profile_resampling():
     rk = (np.arange(64) + 0.5) * s2.rmax / 64
     want = np.interp(rk, rc, row)
     assert np.max(np.abs(prof - want)) <= 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["pr", "lod"])
+def test_threaded_steps_bit_identical(scheme):
+    """The OpenMP line loop (the paper's CPU parallelisation, used for the
+    CPU baseline) solves every line by the same operations as the serial
+    reference, so the fields agree bit for bit, masked cells included."""
+    s = W.production(4, nr=70, nz=133, scheme=scheme).replace(dt=3e-3, t_inf=(0.0, 0.2, -0.1, 0.05))
+    P = oracle.Problem.from_spec(s)
+    T0 = P.initial(0.25)
+    want, _ = P.step(T0, scheme, s.dt, 6)
+    for threads in (1, 2, 5):
+        got, used = P.step_threads(T0, scheme, s.dt, 6, threads)
+        assert 1 <= used <= threads
+        assert np.array_equal(got, want), threads
+    with pytest.raises(ValueError):
+        P.step_threads(T0, scheme, s.dt, 1, 0)
