@@ -124,6 +124,20 @@ def test_strip_layout_shapes_ragged(dshape):
         pytest.skip("shape covers none of the line lengths")
 
 
+@pytest.mark.parametrize("nr,nz", [(2048, 3072), (2045, 3069)], ids=["max", "max_ragged"])
+def test_strip_layout_maximum_line_lengths(nr, nz):
+    """The longest lines the strip kernels take (2048-cell rows, 3072-cell
+    columns) and a ragged grid just below them (a partial strip and a
+    partial row group), in the default strip shapes, with ambient films and
+    a non-zero start: full field against the oracle."""
+    s = W.production(2, nr=nr, nz=nz).replace(dt=1e-3, t_inf=(0.0, 0.2, -0.1, 0.05), T0=0.1)
+    _say("strip layout at the maximum line lengths: %dx%d" % (nr, nz))
+    P, want, _ = run_oracle(s, 2)
+    p, got = run_gpu(s, 2, layout="strips")
+    assert p.layout() == "strips"
+    assert rel_inf(got, want, P.active()) <= TOL
+
+
 @pytest.mark.parametrize("scheme", ["pr", "lod"])
 def test_strip_layout_ambient_films_and_checks(scheme):
     """Strip layout with non-zero ambient temperatures on every face class
