@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(64 * NW) k_batch(BatchArgs a) {
     double* work = (double*)(ws + Ly.work);
     for (int c = 0; c < 3; ++c) {
       assemble_class(P, g, 0, c, kBR_G, Mr, rpos + c * P_NFIELDS * kBR_G * Mr, rchk + c * C_NFIELDS * kBR_G,
-                     reng + c * 2 * nr, rxc + c * nr, work);
+                     reng + c * 2 * nr, rxc + c * nr, work, false);
       if (threadIdx.x == 0) {
         LineTab t;
         t.pos = rpos + c * P_NFIELDS * kBR_G * Mr;
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(64 * NW) k_batch(BatchArgs a) {
     }
     for (int c = 0; c < 4; ++c) {
       assemble_class(P, g, 1, c, kBZ_G, Mz, zpos + c * P_NFIELDS * kBZ_G * Mz, zchk + c * C_NFIELDS * kBZ_G,
-                     zeng + c * 2 * nz, zxc + c * nz, work);
+                     zeng + c * 2 * nz, zxc + c * nz, work, false);
       if (threadIdx.x == 0) {
         LineTab t;
         t.pos = zpos + c * P_NFIELDS * kBZ_G * Mz;
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(64 * NW) k_batch(BatchArgs a) {
       const int GM = kBZ_G * Mz;
       const double* pz = zpos + kap * P_NFIELDS * GM;
       const int ix = (j % Mz) * kBZ_G + j / Mz;
-      dA[cidx] = (pz[P_OD * GM + ix] + pz[P_OL * GM + ix] + pz[P_OU * GM + ix]) * I.T0 + pz[P_OC * GM + ix] +
+      dA[cidx] = (pz[pos_at(P_OD, GM, ix, false)] + pz[pos_at(P_OL, GM, ix, false)] + pz[pos_at(P_OU, GM, ix, false)]) * I.T0 + pz[pos_at(P_OC, GM, ix, false)] +
                  rxc[bet * nr + i];
     }
     __syncthreads();

@@ -120,10 +120,10 @@ __device__ void batch_strip_prologue(const BatchInst& I, char* ws, const BatchLa
   const long rGM = (long)kBS_G * kBSR_M, zGM = (long)Gz * Mz;
   for (int c = 0; c < 3; ++c)
     assemble_class(P, g, 0, c, kBS_G, kBSR_M, rpos + c * P_NFIELDS * rGM, rchk + c * C_NFIELDS * kBS_G,
-                   reng + c * 2 * nr, rxc + c * nr, work);
+                   reng + c * 2 * nr, rxc + c * nr, work, false);
   for (int c = 0; c < 4; ++c)
     assemble_class(P, g, 1, c, Gz, Mz, zpos + c * P_NFIELDS * zGM, zchk + c * C_NFIELDS * Gz,
-                   zeng + c * 2 * nz, zxc + c * nz, work);
+                   zeng + c * 2 * nz, zxc + c * nz, work, false);
   // sweep arguments (uniform across the workgroup; read on use)
   if (threadIdx.x == 0) {
     bool ambient = false;
@@ -174,8 +174,8 @@ __device__ void batch_strip_prologue(const BatchInst& I, char* ws, const BatchLa
       if (region_of(bet, kap) != MASKED) {
         const double* pz = zpos + kap * P_NFIELDS * zGM;
         const long ix = (long)(j % Mz) * Gz + j / Mz;
-        o = (pz[P_OD * zGM + ix] + pz[P_OL * zGM + ix] * (j > 0) + pz[P_OU * zGM + ix] * (j < nz - 1)) * I.T0 +
-            pz[P_OC * zGM + ix] + rxc[bet * nr + i];
+        o = (pz[pos_at(P_OD, zGM, ix, false)] + pz[pos_at(P_OL, zGM, ix, false)] * (j > 0) + pz[pos_at(P_OU, zGM, ix, false)] * (j < nz - 1)) * I.T0 +
+            pz[pos_at(P_OC, zGM, ix, false)] + rxc[bet * nr + i];
       }
     }
     dA[e] = o;

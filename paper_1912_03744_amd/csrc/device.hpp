@@ -96,6 +96,26 @@ enum ChkField {
   C_NFIELDS
 };
 
+// Table layout.  Plain: field f of position ix (= t*G + k) at f*GM + ix, of
+// chunk k at f*G + k.  Paired (the tables of the strip-layout sweeps): the
+// fields those kernels load together are stored as interleaved pairs, so
+// that one 16-byte load per lane fetches both: (w, qa), (cp, sp), (oc, ok)
+// of the positions and (cs, ae), (W0, Q0), (C0, W1), (Q1, C1) of the chunks;
+// the other fields stay plain arrays.
+__host__ __device__ constexpr bool pos_paired(int f) {
+  return f == P_W || f == P_QA || f == P_CP || f == P_SP || f == P_OC || f == P_OK;
+}
+__host__ __device__ constexpr long pos_at(int f, long GM, long ix, bool paired) {
+  return paired && pos_paired(f) ? (long)(f & ~1) * GM + 2 * ix + (f & 1) : (long)f * GM + ix;
+}
+__host__ __device__ constexpr long chk_at(int f, long G, long k, bool paired) {
+  return paired && f < C_CPREV ? (long)(f & ~1) * G + 2 * k + (f & 1) : (long)f * G + k;
+}
+static_assert(P_QA == P_W + 1 && (P_W & 1) == 0 && P_SP == P_CP + 1 && (P_CP & 1) == 0 &&
+              P_OK == P_OC + 1 && (P_OC & 1) == 0, "paired position fields");
+static_assert(C_AE == C_CS + 1 && C_CS == 0 && C_Q0 == C_W0 + 1 && C_W0 == 2 && C_W1 == C_C0 + 1 &&
+              C_C0 == 4 && C_C1 == C_Q1 + 1 && C_Q1 == 6 && C_CPREV == 8, "paired chunk fields");
+
 // One line class in one direction.
 struct LineTab {
   const double* pos;   // [P_NFIELDS][G*M]
@@ -304,7 +324,8 @@ __host__ __device__ constexpr long assemble_work(int G, int M) { return 3L * G *
 //  weights, xc: [n] boundary constants of this direction (the other
 //  direction's sweeps add them), work: assemble_work(G, M) doubles.
 __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls, int G, int M,
-                               double* pos, double* chk, double* eng, double* xc, double* work) {
+                               double* pos, double* chk, double* eng, double* xc, double* work,
+                               bool paired) {
   const int n = dir == 0 ? P.nr : P.nz;
   const int GM = G * M;
   double* A = work;
@@ -322,11 +343,11 @@ __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls,
     const RowCoef R = row_coef(P, g, dir, cls, p);
     A[p] = R.a; B[p] = R.b; Cc[p] = R.c;
     const int ix = (p % M) * G + p / M;
-    pos[P_OD * GM + ix] = R.od;
-    pos[P_OL * GM + ix] = R.ol;
-    pos[P_OU * GM + ix] = R.ou;
-    pos[P_OC * GM + ix] = R.oc;
-    pos[P_OK * GM + ix] = R.ok;
+    pos[pos_at(P_OD, GM, ix, paired)] = R.od;
+    pos[pos_at(P_OL, GM, ix, paired)] = R.ol;
+    pos[pos_at(P_OU, GM, ix, paired)] = R.ou;
+    pos[pos_at(P_OC, GM, ix, paired)] = R.oc;
+    pos[pos_at(P_OK, GM, ix, paired)] = R.ok;
     if (p < n) {
       eng[p] = R.bw;
       eng[n + p] = R.bt;
@@ -339,7 +360,7 @@ __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls,
   // spikes, and the chunk's two rows of the reduced system.
   for (int k = threadIdx.x; k < G; k += blockDim.x) {
     const int s = k * M;
-    auto at = [&](int f, int t) -> double& { return pos[f * GM + t * G + k]; };
+    auto at = [&](int f, int t) -> double& { return pos[pos_at(f, GM, (long)t * G + k, paired)]; };
     at(P_W, 0) = at(P_QA, 0) = at(P_CP, 0) = at(P_SP, 0) = at(P_SR, 0) = 0.0;
     at(P_W, M - 1) = at(P_QA, M - 1) = at(P_CP, M - 1) = at(P_SP, M - 1) = at(P_SR, M - 1) = 0.0;
     double cprev = 0.0, sp = 0.0;
@@ -373,8 +394,8 @@ __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls,
     rlo[2 * k + 1] = -A[e] * Pl;
     rdi[2 * k + 1] = B[e] - A[e] * Rl;
     rup[2 * k + 1] = Cc[e];
-    chk[C_CS * G + k] = Cc[s];
-    chk[C_AE * G + k] = A[e];
+    chk[chk_at(C_CS, G, k, paired)] = Cc[s];
+    chk[chk_at(C_AE, G, k, paired)] = A[e];
   }
   __syncthreads();
 
@@ -394,13 +415,13 @@ __device__ void assemble_class(const Params& P, const Geom& g, int dir, int cls,
 
   // Phase 4: per-chunk factors of the reduced system.
   for (int k = threadIdx.x; k < G; k += blockDim.x) {
-    chk[C_W0 * G + k] = rW[2 * k];
-    chk[C_Q0 * G + k] = rQ[2 * k];
-    chk[C_C0 * G + k] = rC[2 * k];
-    chk[C_W1 * G + k] = rW[2 * k + 1];
-    chk[C_Q1 * G + k] = rQ[2 * k + 1];
-    chk[C_C1 * G + k] = rC[2 * k + 1];
-    chk[C_CPREV * G + k] = k > 0 ? rC[2 * k - 1] : 0.0;
+    chk[chk_at(C_W0, G, k, paired)] = rW[2 * k];
+    chk[chk_at(C_Q0, G, k, paired)] = rQ[2 * k];
+    chk[chk_at(C_C0, G, k, paired)] = rC[2 * k];
+    chk[chk_at(C_W1, G, k, paired)] = rW[2 * k + 1];
+    chk[chk_at(C_Q1, G, k, paired)] = rQ[2 * k + 1];
+    chk[chk_at(C_C1, G, k, paired)] = rC[2 * k + 1];
+    chk[chk_at(C_CPREV, G, k, paired)] = k > 0 ? rC[2 * k - 1] : 0.0;
   }
   __syncthreads();
 }
@@ -621,7 +642,7 @@ __device__ __forceinline__ void solve_group(const SweepArgs& a, int group, doubl
   const int Lfirst = a.cls_l0[c] + (group - a.cls_g0[c]) * (LPW * R) + li * R;
   const int Lend = valid ? a.cls_l1[c] : 0;
   const LineTab tb = a.tabs[c];
-  const double* __restrict__ pos = tb.pos + k;
+  const double* __restrict__ pos = tb.pos + k;  // plain tables (pos_at, chk_at)
   const double* __restrict__ chk = tb.chk + k;
   const int p0 = k * M;
 
@@ -831,7 +852,8 @@ typedef const __attribute__((address_space(1))) double* gptr;
 
 // The factor-table values one lane needs for its chunk k of a line class:
 // interior factors (rows 1..M-2), output scale and constant (all rows),
-// reduced-system factors of the chunk.  Loaded once, ahead of the data.
+// reduced-system factors of the chunk.  Loaded once, right behind the
+// data loads.
 template <int M>
 struct LaneTab {
   double w[M], qa[M], cp[M], sp[M], sr[M];
@@ -840,28 +862,58 @@ struct LaneTab {
 };
 
 // pos/chk: the class tables (uniform across the workgroup), k: the lane's
-// chunk, G chunks.  Every load is a uniform base plus the lane offset k.
-template <int M, int G>
+// chunk, G chunks.  Every load is a uniform base plus a lane offset.  PAIRS:
+// paired tables, each pair of fields in one 16-byte load (the single
+// problem's strip sweeps, whose table loads cost per instruction); else
+// plain tables, one value per load (the batch kernels: the paired layout's
+// second lane stride costs them registers and occupancy).
+template <int M, int G, bool PAIRS>
 __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, const double* chk_, int k) {
+  static_assert(G % 2 == 0, "paired fields need 16-byte aligned field arrays");
   constexpr int GM = G * M;
   const gptr pos = (gptr)pos_;
   const gptr chk = (gptr)chk_;
+  if constexpr (PAIRS) {
+    // half the load instructions (the sweeps' table loads cost per instruction)
+    auto pair = [](const double* p) { return *(const double2*)p; };  // 16-byte aligned
 #pragma unroll
-  for (int t = 1; t <= M - 2; ++t) {
-    L.w[t] = pos[P_W * GM + t * G + k];
-    L.qa[t] = pos[P_QA * GM + t * G + k];
-    L.cp[t] = pos[P_CP * GM + t * G + k];
-    L.sp[t] = pos[P_SP * GM + t * G + k];
-    L.sr[t] = pos[P_SR * GM + t * G + k];
-  }
+    for (int t = 1; t <= M - 2; ++t) {
+      const double2 wq = pair(pos_ + pos_at(P_W, GM, t * G + k, true));
+      const double2 cs = pair(pos_ + pos_at(P_CP, GM, t * G + k, true));
+      L.w[t] = wq.x; L.qa[t] = wq.y;
+      L.cp[t] = cs.x; L.sp[t] = cs.y;
+      L.sr[t] = pos[pos_at(P_SR, GM, t * G + k, true)];
+    }
 #pragma unroll
-  for (int t = 0; t < M; ++t) {
-    L.ok[t] = pos[P_OK * GM + t * G + k];
-    L.oc[t] = pos[P_OC * GM + t * G + k];
+    for (int t = 0; t < M; ++t) {
+      const double2 ck = pair(pos_ + pos_at(P_OC, GM, t * G + k, true));
+      L.oc[t] = ck.x; L.ok[t] = ck.y;
+    }
+    const double2 c0 = pair(chk_ + chk_at(C_CS, G, k, true)), c1 = pair(chk_ + chk_at(C_W0, G, k, true));
+    const double2 c2 = pair(chk_ + chk_at(C_C0, G, k, true)), c3 = pair(chk_ + chk_at(C_Q1, G, k, true));
+    L.cs = c0.x; L.ae = c0.y;
+    L.W0 = c1.x; L.Q0 = c1.y;
+    L.C0 = c2.x; L.W1 = c2.y;
+    L.Q1 = c3.x; L.C1 = c3.y;
+  } else {
+    // plain tables, one value per load
+#pragma unroll
+    for (int t = 1; t <= M - 2; ++t) {
+      L.w[t] = pos[P_W * GM + t * G + k];
+      L.qa[t] = pos[P_QA * GM + t * G + k];
+      L.cp[t] = pos[P_CP * GM + t * G + k];
+      L.sp[t] = pos[P_SP * GM + t * G + k];
+      L.sr[t] = pos[P_SR * GM + t * G + k];
+    }
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+      L.ok[t] = pos[P_OK * GM + t * G + k];
+      L.oc[t] = pos[P_OC * GM + t * G + k];
+    }
+    L.cs = chk[C_CS * G + k]; L.ae = chk[C_AE * G + k];
+    L.W0 = chk[C_W0 * G + k]; L.Q0 = chk[C_Q0 * G + k]; L.C0 = chk[C_C0 * G + k];
+    L.W1 = chk[C_W1 * G + k]; L.Q1 = chk[C_Q1 * G + k]; L.C1 = chk[C_C1 * G + k];
   }
-  L.cs = chk[C_CS * G + k]; L.ae = chk[C_AE * G + k];
-  L.W0 = chk[C_W0 * G + k]; L.Q0 = chk[C_Q0 * G + k]; L.C0 = chk[C_C0 * G + k];
-  L.W1 = chk[C_W1 * G + k]; L.Q1 = chk[C_Q1 * G + k]; L.C1 = chk[C_C1 * G + k];
 }
 
 // Solve a block of R lines in place.  Lane k = 64*wave + lane holds chunk

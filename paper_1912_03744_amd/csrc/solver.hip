@@ -125,6 +125,7 @@ struct DirTabs {
   LineTab* tabs;
   double *pos, *chk, *eng, *xc, *work;
   int ncls, n, G, M;
+  int paired;  // tables in the paired layout (read by the strip-layout sweeps)
 };
 
 // One workgroup per line class: r bands first, then z column classes.
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(256) k_assemble(Params P, Geom g, DirTabs r, D
   double* eng = D.eng + (long)cls * 2 * D.n;
   double* xc = D.xc + (long)cls * D.n;
   double* work = D.work + cls * assemble_work(D.G, D.M);
-  assemble_class(P, g, dir, cls, D.G, D.M, pos, chk, eng, xc, work);
+  assemble_class(P, g, dir, cls, D.G, D.M, pos, chk, eng, xc, work, D.paired != 0);
   if (threadIdx.x == 0) {
     // cells outside the domain form one contiguous run of a line
     int lo = D.n, hi = D.n, cnt = 0;
@@ -189,9 +190,9 @@ __global__ void k_init_rhs(const double* __restrict__ T, double* __restrict__ d,
         const long GM = (long)z.G * z.M;
         const double* pos = z.pos + kap * P_NFIELDS * GM;
         const long ix = (long)(j % z.M) * z.G + j / z.M;
-        o = pos[P_OD * GM + ix] * T[c] + pos[P_OC * GM + ix] + rxc[(long)bet * nr + i];
-        if (j > 0) o += pos[P_OL * GM + ix] * T[c - nr];
-        if (j < nz - 1) o += pos[P_OU * GM + ix] * T[c + nr];
+        o = pos[pos_at(P_OD, GM, ix, z.paired != 0)] * T[c] + pos[pos_at(P_OC, GM, ix, z.paired != 0)] + rxc[(long)bet * nr + i];
+        if (j > 0) o += pos[pos_at(P_OL, GM, ix, z.paired != 0)] * T[c - nr];
+        if (j < nz - 1) o += pos[pos_at(P_OU, GM, ix, z.paired != 0)] * T[c + nr];
       }
     }
     d[e] = o;
@@ -421,6 +422,7 @@ struct DirState {
     DirTabs d;
     d.tabs = tabs; d.pos = pos; d.chk = chk; d.eng = eng; d.xc = xc; d.work = work;
     d.ncls = ncls; d.n = n; d.G = L.G; d.M = L.M;
+    d.paired = L.layout == ADI_LAYOUT_STRIPS;  // the strip sweeps read pairs
     return d;
   }
 };

@@ -323,7 +323,7 @@ __device__ __forceinline__ void strip_z_body(const StripArgs& a, int s, int tid,
   zero_past_edge<M>(mine_slots, nact);
   for (int c = c_lo; c <= c_hi; ++c) {
     LaneTab<M> L;  // behind the data loads; live for one pass only
-    load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
+    load_lanetab<M, NT, false>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
     z_pass<M, NW, 4>(a, c0, tid, mine_slots, L, L, carry, false, block_lines_of(a, c0, nact, c));
   }
   wave_sync();
@@ -359,8 +359,8 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_zs(StripArgs a) {
   LaneTab<M> LA, LB;
   {
     const int ca = rev ? c_hi : c;
-    load_lanetab<M, NT>(LA, a.tabs[ca].pos, a.tabs[ca].chk, tid);
-    if (split) load_lanetab<M, NT>(LB, a.tabs[rev ? c_lo : c_hi].pos, a.tabs[rev ? c_lo : c_hi].chk, tid);
+    load_lanetab<M, NT, true>(LA, a.tabs[ca].pos, a.tabs[ca].chk, tid);
+    if (split) load_lanetab<M, NT, true>(LB, a.tabs[rev ? c_lo : c_hi].pos, a.tabs[rev ? c_lo : c_hi].chk, tid);
   }
   wave_sync();
   double* mine_slots = buf + tid * 4 * M;
@@ -410,7 +410,7 @@ __device__ __forceinline__ void strip_r_body(const StripArgs& a, int J, int tid,
   auto rhs = [&](int r, int t) { return mine_slots[r * 4 + t]; };
   for (int c = c_lo; c <= c_hi; ++c) {
     LaneTab<M> L;  // behind the data loads; live for one pass only
-    load_lanetab<M, NT>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
+    load_lanetab<M, NT, false>(L, a.tabs[c].pos, a.tabs[c].chk, tid);
     const unsigned mask = block_lines_of(a, j0, nact, c);
     double v[4][M];
 #pragma unroll
@@ -488,7 +488,7 @@ __device__ __forceinline__ void strip_r_slots(const StripArgs& a, int J0, double
     }
   for (int c = c_lo; c <= c_hi; ++c) {
     LaneTab<M> L;  // behind the data loads; live for one pass only
-    load_lanetab<M, 64>(L, a.tabs[c].pos, a.tabs[c].chk, ci);
+    load_lanetab<M, 64, false>(L, a.tabs[c].pos, a.tabs[c].chk, ci);
     const unsigned mask = block_lines_of(a, j0, nact, c);
     double v[4][M];
 #pragma unroll
@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(64 * NW) k_sweep_rs(StripArgs a) {
     *(double2*)&buf[st * CH + (q & 7) * 2] = x;
   }
   LaneTab<M> L;  // behind the data loads
-  load_lanetab<M, NT>(L, tb.pos, tb.chk, tid);
+  load_lanetab<M, NT, true>(L, tb.pos, tb.chk, tid);
   wave_sync();
   double* mine_slots = buf + tid * CH;
   if (lc < 0) {

@@ -47,7 +47,7 @@ int run(Params P, double dt, int nsteps, int scheme, double T0, const char* out)
       double* chk = X.chk.data() + (long)c * C_NFIELDS * X.G;
       emu_launch(1, 64, [&] {
         assemble_class(P, g, d, c, X.G, X.M, pos, chk, X.eng.data() + (long)c * 2 * X.n,
-                       X.xc.data() + (long)c * X.n, X.work.data() + c * assemble_work(X.G, X.M));
+                       X.xc.data() + (long)c * X.n, X.work.data() + c * assemble_work(X.G, X.M), true);
       });
       // the run of cells outside the domain along a line of this class
       int lo = X.n, hi = X.n, cnt = 0;
@@ -80,9 +80,9 @@ int run(Params P, double dt, int nsteps, int scheme, double T0, const char* out)
         if (region_of(bt, kp) == MASKED) continue;
         const double* pos = Z.pos.data() + kp * P_NFIELDS * GM;
         const long ix = (long)(j % Z.M) * Z.G + j / Z.M;
-        double o = pos[P_OD * GM + ix] * T[c] + pos[P_OC * GM + ix] + D[0].xc[(long)bt * nr + i];
-        if (j > 0) o += pos[P_OL * GM + ix] * T[c - nr];
-        if (j < nz - 1) o += pos[P_OU * GM + ix] * T[c + nr];
+        double o = pos[pos_at(P_OD, GM, ix, true)] * T[c] + pos[pos_at(P_OC, GM, ix, true)] + D[0].xc[(long)bt * nr + i];
+        if (j > 0) o += pos[pos_at(P_OL, GM, ix, true)] * T[c - nr];
+        if (j < nz - 1) o += pos[pos_at(P_OU, GM, ix, true)] * T[c + nr];
         dA[(long)(i >> 2) * strip + 4L * j + (i & 3)] = o;
       }
   }
