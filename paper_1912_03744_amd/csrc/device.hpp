@@ -865,15 +865,15 @@ struct LaneTab {
 // chunk, G chunks.  Every load is a uniform base plus a lane offset.  PAIRS:
 // paired tables, each pair of fields in one 16-byte load (the single
 // problem's strip sweeps, whose table loads cost per instruction); else
-// plain tables, one value per load (the batch kernels: the paired layout's
-// second lane stride costs them registers and occupancy).
+// plain tables, one value per load (the batch kernels, which the paired
+// layout costs registers and occupancy).
 template <int M, int G, bool PAIRS>
 __device__ __forceinline__ void load_lanetab(LaneTab<M>& L, const double* pos_, const double* chk_, int k) {
-  static_assert(G % 2 == 0, "paired fields need 16-byte aligned field arrays");
   constexpr int GM = G * M;
   const gptr pos = (gptr)pos_;
   const gptr chk = (gptr)chk_;
   if constexpr (PAIRS) {
+    static_assert(G % 2 == 0, "paired fields need 16-byte aligned field arrays");
     // half the load instructions (the sweeps' table loads cost per instruction)
     auto pair = [](const double* p) { return *(const double2*)p; };  // 16-byte aligned
 #pragma unroll
