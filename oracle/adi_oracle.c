@@ -192,6 +192,10 @@ or_problem *or_create(const double *geom, int nr, int nz, const double *rfaces,
       if (i == 0) {
         /* axis r = 0: the face radius is zero, no flux */
       } else if (p->region[c - 1] == OR_MASKED) {
+        /* Never reached on the layout of Fig. 1: cells outside the domain
+         * lie at r >= r0 and every active cell of their rows at r < r0, so
+         * a cut-out cell is never west of an active one.  Kept so that the
+         * operator stays defined for any region map. */
         double g = series_g(p->dr[i], kc, p->h[3]);
         p->Lr_c[c] -= p->rf[i] * g / vol_r;
         p->br[c] += p->rf[i] * g * p->tinf[3] / vol_r;
