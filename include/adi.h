@@ -196,7 +196,11 @@ adi_status adi_get_layout(adi_problem p, int32_t* layout);
 /* Wait until all work enqueued on the problem's stream has finished. */
 adi_status adi_sync(adi_problem p);
 
-/* Steps per captured HIP graph in adi_step (0 = plain launches). */
+/* Graphs in adi_step: with steps = K > 0, adi_step replays captured HIP
+ * graphs of K steps and of every power of two below K (each run of steps
+ * between energy checks as whole graphs, largest first), captured together
+ * on the first call after the tables or the check pattern change; 0 = plain
+ * launches.  K <= 4096. */
 adi_status adi_set_graph_steps(adi_problem p, int32_t steps);
 
 void adi_destroy(adi_problem p);
@@ -236,18 +240,28 @@ adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t wav
 /* Advance every instance nsteps steps of size dt from its initial field
  * (each call starts again from the initial fields), recording the outer
  * terminal-face profile (top row resampled at r_k = (k+0.5)*rmax/npts, as in
- * adi_read_profile) after every snapshot_every-th step (0 = none).  Enqueued
- * on the batch's stream as captured HIP graphs: one for the persistent
- * kernel (queue reset + kernel), or, for the batched sweep launches, one per
- * 256 steps (the instance set-up in the first); returns without waiting. */
-adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapshot_every, int32_t npts);
+ * adi_read_profile) after every snapshot_every-th step (0 = none).
+ * dev_profiles: NULL, or a device buffer of the caller (at least n * nsnap *
+ * npts doubles, nsnap = nsteps/snapshot_every, instance-major, then
+ * snapshot, then point) that receives the snapshots instead of the batch's
+ * own buffer, e.g. a torch tensor; it must stay allocated until the work of
+ * this call has finished.  npts is an argument of this call (not only of
+ * the read) because the snapshots are resampled on the device as they are
+ * taken.  Enqueued on the batch's stream as captured HIP graphs: one for the
+ * persistent kernel (queue reset + kernel), or, for the batched sweep
+ * launches, one per 256 steps (the instance set-up in the first); returns
+ * without waiting. */
+adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapshot_every, int32_t npts,
+                          double* dev_profiles);
 
 /* Wait for the batch's stream. */
 adi_status adi_batch_sync(adi_batch b);
 
-/* Profiles of the last adi_batch_step: count = n * (nsteps/snapshot_every) *
- * npts doubles, instance-major, then snapshot, then point.  Synchronises. */
-adi_status adi_batch_read_profiles(adi_batch b, double* host_out, size_t count);
+/* Profiles of the last adi_batch_step, from the batch's own buffer or the
+ * caller's dev_profiles: npts must equal that call's npts; count = n *
+ * (nsteps/snapshot_every) * npts doubles, instance-major, then snapshot,
+ * then point.  Synchronises. */
+adi_status adi_batch_read_profiles(adi_batch b, int32_t npts, double* host_out, size_t count);
 
 /* Final field of instance i (nz*nr doubles, r fastest; cells outside the
  * domain hold 0).  Synchronises. */
@@ -261,7 +275,7 @@ adi_status adi_batch_info(adi_batch b, int64_t* total_cells, int32_t* nsnap, int
 /* Cells inside the domain (not masked) summed over all instances. */
 adi_status adi_batch_active_cells(adi_batch b, int64_t* active);
 
-/* Run adi_batch_step(b, dt, nsteps, 0, 64) reps times back to back,
+/* Run adi_batch_step(b, dt, nsteps, 0, 64, NULL) reps times back to back,
  * bracketed by HIP events on the batch's stream, and return the mean
  * milliseconds per call (launch shape as set; fields end as after one call).
  * Synchronises.  Used by the autotuner and the benchmark. */

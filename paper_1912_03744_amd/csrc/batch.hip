@@ -235,7 +235,8 @@ struct adi_batch_s {
   long cells = 0, active = 0;           // cells, cells inside the domain
   long maxstrip = 0;                    // largest right-hand side in the strip layout (doubles)
   double* prof = nullptr;
-  long prof_cap = 0;  // doubles
+  long prof_cap = 0;           // doubles
+  double* prof_out = nullptr;  // where the last step wrote its snapshots (prof or the caller's buffer)
   int nsnap = 0, npts = 64;
   char* scratch = nullptr;
   BatchLayout lay{};
@@ -316,7 +317,7 @@ void launch_sweeps(adi_batch b, int64_t st0, int64_t st1, int64_t nsteps, int sn
   a.args = b->sargs;
   a.n = b->n;
   a.T = b->T;
-  a.prof = b->prof;
+  a.prof = b->prof_out;
   a.npts = npts;
   a.map = b->smap;
   if (st0 == 1) hipLaunchKernelGGL(k_bsetup, dim3(b->n), dim3(256), 0, b->stream, a);
@@ -504,7 +505,8 @@ adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t wav
   return ADI_OK;
 }
 
-adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapshot_every, int32_t npts) {
+adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapshot_every, int32_t npts,
+                          double* dev_profiles) {
   ADI_TRY(batch_handle(b));
   if (!b->has_mat) return fail(ADI_ESTATE, "adi_batch_set_materials must be called before stepping");
   if (!(dt > 0.0) || !is_fin(dt)) return fail(ADI_EINVAL, "dt must be > 0 and finite");
@@ -513,7 +515,7 @@ adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapsh
   if (npts < 1 || npts > 4096) return fail(ADI_EINVAL, "npts must be in [1, 4096]");
   const int nsnap = snapshot_every > 0 ? (int)(nsteps / snapshot_every) : 0;
   const long need = (long)b->n * std::max(nsnap, 1) * npts;
-  if (need > b->prof_cap) {
+  if (!dev_profiles && need > b->prof_cap) {
     ADI_HIP(hipStreamSynchronize(b->stream));
     dev_free(b->prof);
     b->prof = nullptr;
@@ -522,6 +524,7 @@ adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapsh
   }
   b->nsnap = nsnap;
   b->npts = npts;
+  b->prof_out = dev_profiles ? dev_profiles : b->prof;
   for (auto& I : b->hinst) {
     I.P.ta = b->scheme == ADI_PR ? 0.5 * dt : dt;
     I.P.theta = b->scheme == ADI_PR ? 1.0 : 0.0;
@@ -536,7 +539,7 @@ adi_status adi_batch_step(adi_batch b, double dt, int64_t nsteps, int32_t snapsh
   a.ninst = b->n;
   a.queue = b->queue;
   a.T = b->T;
-  a.prof = b->prof;
+  a.prof = b->prof_out;
   a.nsnap = nsnap;
   a.npts = npts;
   a.snap_every = snapshot_every;
@@ -566,12 +569,13 @@ adi_status adi_batch_sync(adi_batch b) {
   return ADI_OK;
 }
 
-adi_status adi_batch_read_profiles(adi_batch b, double* host_out, size_t count) {
+adi_status adi_batch_read_profiles(adi_batch b, int32_t npts, double* host_out, size_t count) {
   ADI_TRY(batch_handle(b));
   if (!host_out) return fail(ADI_EINVAL, "null output buffer");
+  if (npts != b->npts) return fail(ADI_EINVAL, "npts %d != %d, the points per profile of the last step", npts, b->npts);
   const size_t n = (size_t)b->n * b->nsnap * b->npts;
   if (count != n) return fail(ADI_EINVAL, "count %zu != n*nsnap*npts = %zu", count, n);
-  if (n) ADI_HIP(hipMemcpyAsync(host_out, b->prof, sizeof(double) * n, hipMemcpyDeviceToHost, b->stream));
+  if (n) ADI_HIP(hipMemcpyAsync(host_out, b->prof_out, sizeof(double) * n, hipMemcpyDefault, b->stream));
   ADI_HIP(hipStreamSynchronize(b->stream));
   return ADI_OK;
 }
@@ -612,7 +616,7 @@ adi_status adi_batch_time(adi_batch b, double dt, int64_t nsteps, int32_t reps, 
   for (auto& x : ev) ADI_HIP(hipEventCreate(&x));
   adi_status st = ADI_OK;
   (void)hipEventRecord(ev[0], b->stream);
-  for (int i = 0; i < reps && st == ADI_OK; ++i) st = adi_batch_step(b, dt, nsteps, 0, 64);
+  for (int i = 0; i < reps && st == ADI_OK; ++i) st = adi_batch_step(b, dt, nsteps, 0, 64, nullptr);
   (void)hipEventRecord(ev[1], b->stream);
   hipError_t e = hipEventSynchronize(ev[1]);
   float ms = 0.f;

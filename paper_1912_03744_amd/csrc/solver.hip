@@ -766,6 +766,26 @@ adi_status get_graph(adi_problem p, int n, bool check, hipGraphExec_t* out) {
   return ADI_OK;
 }
 
+// Captured segments of K steps and of every power of two below K, with and
+// without the check in their first step (the latter only when checks run):
+// any run of steps between checks is then a sequence of whole segments
+// (largest first), so every call of adi_step replays graphs, whatever its
+// step count.  All of them are captured at once, on the first call after
+// the tables or the check pattern change.
+adi_status ensure_graph_family(adi_problem p) {
+  if (!p->graphs.empty()) return ADI_OK;
+  const int K = p->graph_steps;
+  for (int c = 0; c < (p->check_every > 0 ? 2 : 1); ++c) {
+    for (int n = 1; n < K; n *= 2) {
+      hipGraphExec_t ex;
+      ADI_TRY(get_graph(p, n, c == 1, &ex));
+    }
+    hipGraphExec_t ex;
+    ADI_TRY(get_graph(p, K, c == 1, &ex));
+  }
+  return ADI_OK;
+}
+
 adi_status sync_and_check(adi_problem p) {
   ADI_HIP(hipStreamSynchronize(p->stream));
   double st[4];
@@ -998,7 +1018,7 @@ adi_status adi_set_check(adi_problem p, int32_t every, double tol) {
 
 adi_status adi_set_graph_steps(adi_problem p, int32_t steps) {
   ADI_TRY(check_handle(p));
-  if (steps < 0 || steps > 100000) return fail(ADI_EINVAL, "graph steps must be in [0, 100000]");
+  if (steps < 0 || steps > 4096) return fail(ADI_EINVAL, "graph steps must be in [0, 4096]");
   p->graph_steps = steps;
   drop_graphs(p);
   return ADI_OK;
@@ -1034,17 +1054,22 @@ adi_status adi_step(adi_problem p, double dt, int64_t nsteps) {
       seg = std::min<int64_t>(seg, is_check_step(p, gs) ? p->check_every : to_next);
     }
     const bool check = is_check_step(p, gs);
-    if (K > 0 && seg >= K) {
-      // whole captured segments of K steps where the pattern allows it
-      const int64_t reps = seg / K;
-      const bool pattern_ok = !(p->check_every > 0) || (check && K == p->check_every);
-      if (pattern_ok || (!check && p->check_every == 0)) {
+    if (K > 0) {
+      ADI_TRY(ensure_graph_family(p));
+      for (int64_t done = 0; done < seg;) {
+        const int64_t rem = seg - done;
+        int n = K;
+        if (rem < K) {
+          n = 1;
+          while (2 * (int64_t)n <= rem) n *= 2;
+        }
         hipGraphExec_t ex;
-        ADI_TRY(get_graph(p, K, check, &ex));
-        for (int64_t r = 0; r < reps; ++r) ADI_HIP(hipGraphLaunch(ex, p->stream));
-        s += reps * K;
-        continue;
+        ADI_TRY(get_graph(p, n, check && done == 0, &ex));
+        ADI_HIP(hipGraphLaunch(ex, p->stream));
+        done += n;
       }
+      s += seg;
+      continue;
     }
     ADI_TRY(enqueue_steps(p, gs, seg));
     s += seg;

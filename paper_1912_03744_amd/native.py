@@ -97,9 +97,9 @@ _SIGS = {
     "adi_batch_set_materials": [_vp, _dp, _dp, _dp],
     "adi_batch_set_initial": [_vp, _dp],
     "adi_batch_set_launch": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
-    "adi_batch_step": [_vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32],
+    "adi_batch_step": [_vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp],
     "adi_batch_sync": [_vp],
-    "adi_batch_read_profiles": [_vp, _dp, ctypes.c_size_t],
+    "adi_batch_read_profiles": [_vp, ctypes.c_int32, _dp, ctypes.c_size_t],
     "adi_batch_read_field": [_vp, ctypes.c_int32, _dp, ctypes.c_size_t],
     "adi_batch_info": [_vp, ctypes.POINTER(ctypes.c_int64), _i32p, _i32p],
     "adi_batch_active_cells": [_vp, ctypes.POINTER(ctypes.c_int64)],
@@ -362,9 +362,22 @@ class Batch:
         check(lib().adi_batch_set_launch(self._h, int(lines_per_lane), int(waves_per_block),
                                          int(blocks_per_cu)))
 
-    def step(self, dt, nsteps, snapshot_every=0, npts=64):
-        check(lib().adi_batch_step(self._h, float(dt), int(nsteps), int(snapshot_every), int(npts)))
-        self._nsnap = int(nsteps) // int(snapshot_every) if snapshot_every else 0
+    def step(self, dt, nsteps, snapshot_every=0, npts=64, out=None):
+        """Advance every instance from its initial field.  out: None, or a
+        float64 CUDA tensor of n * (nsteps // snapshot_every) * npts elements
+        that receives the profile snapshots on the device (it must stay alive
+        until the batch's stream has finished the call)."""
+        nsnap = int(nsteps) // int(snapshot_every) if snapshot_every else 0
+        dev = None
+        if out is not None:
+            if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()):
+                raise ValueError("out must be a contiguous float64 CUDA tensor")
+            if out.numel() < self.n * nsnap * int(npts):
+                raise ValueError("out holds %d values, the snapshots need %d" % (out.numel(), self.n * nsnap * int(npts)))
+            dev = ctypes.c_void_p(out.data_ptr())
+            _torch_stream_sync()
+        check(lib().adi_batch_step(self._h, float(dt), int(nsteps), int(snapshot_every), int(npts), dev))
+        self._nsnap = nsnap
         self._npts = int(npts)
 
     def sync(self):
@@ -372,7 +385,7 @@ class Batch:
 
     def profiles(self):
         out = np.empty((self.n, self._nsnap, self._npts))
-        check(lib().adi_batch_read_profiles(self._h, _ptr(out), out.size))
+        check(lib().adi_batch_read_profiles(self._h, self._npts, _ptr(out), out.size))
         return out
 
     def field(self, i):

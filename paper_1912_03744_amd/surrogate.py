@@ -83,22 +83,24 @@ def solve_profiles(D: np.ndarray, nsteps=2000, dt=1e-3, snap_every=100, grid=LAB
     """Terminal-face profiles of designs D (rows of 11 parameters) from the
     batched FP64 solver (by default as batched sweep launches): [n,
     nsteps // snap_every, 64]."""
+    import torch
     n = len(D)
-    nsnap = nsteps // snap_every if snap_every else 0
-    out = np.empty((n, max(nsnap, 1), NPTS))
+    every = snap_every if snap_every else nsteps
+    nsnap = nsteps // every
+    out = torch.empty((n, nsnap, NPTS), dtype=torch.float64, device="cuda")
     for a in range(0, n, chunk):
         specs = [W.design_spec(W.design_from_row(x), *grid, dt=dt, nsteps=nsteps) for x in D[a:a + chunk]]
         b = native.Batch(specs)
         b.set_launch(*launch)
         t0 = time.perf_counter()
-        b.step(dt, nsteps, snapshot_every=snap_every if snap_every else nsteps, npts=NPTS)
-        prof = b.profiles()
+        # the snapshots go straight into the device tensor
+        b.step(dt, nsteps, snapshot_every=every, npts=NPTS, out=out[a:a + len(specs)])
+        b.sync()
         if log:
             log("solved %d designs (%dx%d, %d steps) in %.2f s" % (len(specs), grid[0], grid[1], nsteps,
                                                                  time.perf_counter() - t0))
-        out[a:a + len(specs)] = prof
         b.close()
-    return out
+    return out.cpu().numpy()
 
 
 def make_pairs(D: np.ndarray, prof: np.ndarray, snap_dt: float):
