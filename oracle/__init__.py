@@ -61,7 +61,16 @@ def _lib():
                                     ctypes.c_long, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         lib.or_energy.argtypes = [ctypes.c_void_p, _dp, _dp]
         lib.or_profile.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, _dp]
-        for f in ("or_coeffs", "or_step", "or_step_omp", "or_profile"):
+        lib.or_nl_set_laws.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        lib.or_nl_apply.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
+        lib.or_pulse.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
+        lib.or_pulse.restype = ctypes.c_double
+        lib.or_nl_step.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   _dp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]
+        _lp = ctypes.POINTER(ctypes.c_long)
+        lib.or_nl_run.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp,
+                                  ctypes.c_int, ctypes.c_long, _lp, _dp, ctypes.c_long, _dp]
+        for f in ("or_coeffs", "or_step", "or_step_omp", "or_profile", "or_nl_step", "or_nl_run"):
             getattr(lib, f).restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -193,3 +202,76 @@ class Problem:
     def initial(self, T0):
         """Uniform field T0 on active cells, 0 on masked cells."""
         return np.where(self.active(), float(T0), 0.0)
+
+
+# ------------------------------------------------------------ nonlinear --
+# The simple (Picard) iteration of eq. 12-14, the pulsed source of eq. 2-4
+# and the adaptive step of Sec. 3-4 (adi_oracle.c, section "Nonlinear path").
+
+PULSES = {"const": 0, "rect": 1, "erf": 2}
+
+
+def pulse(kind, t, t_per=0.1, t_src=0.01, t_trs=1e-4, xi=4.0, zeta=2.0):
+    """Normalised source p(t): 'const' (1), 'rect' (eq. 3) or 'erf' (eq. 4)."""
+    pp = _f64([t_per, t_src, t_trs, xi, zeta], 5)
+    return _lib().or_pulse(PULSES[kind], float(t), _ptr(pp))
+
+
+class NonlinearProblem(Problem):
+    """A problem with temperature-dependent laws: lam, cap, src are 5 x 4
+    polynomial coefficients (region-major, c0 + c1 T + c2 T^2 + c3 T^3) of
+    the conductivity, the volumetric heat capacity and the source amplitude."""
+
+    def set_laws(self, lam, cap, src):
+        self._laws = [_f64(lam, 20), _f64(cap, 20), _f64(src, 20)]
+        _lib().or_nl_set_laws(self._h, *(_ptr(a) for a in self._laws))
+
+    def set_constant_laws(self, k, rhoc, q):
+        """Laws equal to the linear problem's constants."""
+        z = np.zeros((5, 3))
+        self.set_laws(np.column_stack([k, z]), np.column_stack([rhoc, z]), np.column_stack([q, z]))
+
+    def nl_apply(self, F, T):
+        """(A_r T, A_z T) with the laws evaluated on the field F."""
+        F = _f64(F, self.nr * self.nz)
+        T = _f64(T, self.nr * self.nz)
+        ar, az = np.empty(self.shape), np.empty(self.shape)
+        _lib().or_nl_apply(self._h, _ptr(F), _ptr(T), _ptr(ar), _ptr(az))
+        return ar, az
+
+    def nl_step(self, T, tau, t, kind="const", pulse_args=(0.1, 0.01, 1e-4, 4.0, 2.0), eps=1e-10,
+                iter_max=10):
+        """One step by eq. 12 and 14.  Returns (accepted, T_new, solves,
+        last_changes); T_new is T itself when the step failed."""
+        T = _f64(T, self.nr * self.nz).reshape(self.shape).copy()
+        pp = _f64(pulse_args, 5)
+        it = (ctypes.c_int * 2)()
+        chg = np.zeros(2)
+        ok = _lib().or_nl_step(self._h, _ptr(T), float(tau), float(t), PULSES[kind], _ptr(pp), float(eps),
+                               int(iter_max), it, _ptr(chg))
+        if ok < 0:
+            raise MemoryError("or_nl_step")
+        return bool(ok), T, (it[0], it[1]), chg
+
+    def nl_run(self, T, t0, t_end, kind="erf", pulse_args=(0.1, 0.01, 1e-4, 4.0, 2.0), eps=1e-6,
+               iter_max=10, tau_min=1e-12, periodic_tol=0.0, tau_trs_div=1000.0, tau_src_div=100.0,
+               max_steps=1 << 40, log_cap=0):
+        """The adaptive loop of Sec. 4.  Returns a dict with the field, the
+        final time, the counts and (log_cap > 0) the per-step log rows
+        (t_before, tau, solves_r, solves_z)."""
+        T = _f64(T, self.nr * self.nz).reshape(self.shape).copy()
+        pp = _f64(pulse_args, 5)
+        ctl = _f64([eps, tau_min, periodic_tol, tau_trs_div, tau_src_div], 5)
+        t = np.array([float(t0)])
+        counts = (ctypes.c_long * 5)()
+        log = np.zeros((max(log_cap, 1), 4))
+        margin = np.zeros(1)
+        rc = _lib().or_nl_run(self._h, _ptr(T), _ptr(t), float(t_end), PULSES[kind], _ptr(pp), _ptr(ctl),
+                              int(iter_max), int(max_steps), counts, _ptr(log) if log_cap else None,
+                              int(log_cap), _ptr(margin))
+        if rc != 0:
+            raise ValueError("or_nl_run failed: %d" % rc)
+        steps = counts[0]
+        return {"T": T, "t": float(t[0]), "steps": steps, "rejected": counts[1], "solves_r": counts[2],
+                "solves_z": counts[3], "periodic": bool(counts[4]), "min_margin": float(margin[0]),
+                "log": log[:min(steps, log_cap)] if log_cap else None}

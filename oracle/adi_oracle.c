@@ -84,6 +84,11 @@ typedef struct {
   double *Bw_r, *Bt_r, *Bw_z, *Bt_z;
   double *C, *Q;        /* rho c and source per cell (0 when masked) */
   double *V;            /* control volume r_c dr dz (2 pi dropped) */
+  /* Temperature-dependent material laws of the nonlinear path (Sec. 2,
+   * eq. 1-2): per region, cubic polynomials c0 + c1 T + c2 T^2 + c3 T^3 of
+   * the conductivity lambda, the volumetric heat capacity rho c_V and the
+   * source amplitude chi I^2/S_C; set by or_nl_set_laws. */
+  double lam[5][4], cap[5][4], src[5][4];
 } or_problem;
 
 /* ------------------------------------------------------------------ grid -- */
@@ -519,4 +524,422 @@ int or_profile(const or_problem *p, const double *T, int which, int npts, double
     out[kk] = v;
   }
   return OR_OK;
+}
+
+/* ===================================================================== */
+/*  Nonlinear path: the simple (Picard) iteration of Sec. 3 (eq. 12-14),  */
+/*  the pulsed source of Sec. 2 (eq. 2-4) and the adaptive time step of  */
+/*  Sec. 3 and Sec. 4.                                                   */
+/* ===================================================================== */
+/*
+ * Readings (listed with the others in the design notes):
+ *  - The material laws are not published; each region carries cubic
+ *    polynomials in T for lambda, rho c_V and the source amplitude
+ *    chi(T) I^2/S_C (zero outside the heater for the paper's cell).
+ *  - Face conductivity (the garbled half-node formula after eq. 11): each
+ *    side's lambda is evaluated at the mean of the two cell temperatures
+ *    and the two half cells are combined in series.  Inside one material
+ *    on a uniform grid this is the paper's lambda_m((T_i + T_{i+1})/2)/h;
+ *    with constant laws it is the linear path's harmonic conductance.
+ *    A boundary film uses lambda at the cell's own temperature.
+ *  - The source of both half steps is X at the half layer: chi at the
+ *    iterate (eq. 12) or at T-bar (eq. 14), times p(t + tau/2).
+ *  - Iteration: T^0 = T (eq. 12) or T-bar (eq. 14); stop when the max norm
+ *    of T^{s+1} - T^s over the cells of the domain is below eps (eq. 13);
+ *    a half step that has not stopped after iter_max solves fails.
+ *  - Time step (Sec. 4): at the start of every step tau = t_trs/1000 inside
+ *    a transition of the source (the first t_trs of a switch-on or a
+ *    switch-off) and t_src/100 elsewhere; a step ends no later than the next
+ *    switch point, transition end or t_end, so that transitions are always
+ *    taken with the short step; a failed step is retried with tau/2.
+ *  - Periodic regime (Sec. 4, criterion unstated): at each period start the
+ *    field is compared with the one of the previous period start; the run
+ *    stops once the max norm of the change is below a given tolerance.
+ */
+
+/* c0 + c1 T + c2 T^2 + c3 T^3 */
+static double poly3(const double *c, double T) {
+  return c[0] + T * (c[1] + T * (c[2] + T * c[3]));
+}
+
+/* lam, cap, src: 5 regions x 4 coefficients each, region-major. */
+void or_nl_set_laws(or_problem *p, const double *lam, const double *cap, const double *src) {
+  for (int m = 0; m < 5; ++m)
+    for (int q = 0; q < 4; ++q) {
+      p->lam[m][q] = lam[4 * m + q];
+      p->cap[m][q] = cap[4 * m + q];
+      p->src[m][q] = src[4 * m + q];
+    }
+}
+
+/*
+ * Normalised periodic source p(t) (eq. 2).  kind 0: p = 1; kind 1: the
+ * rectangular pulse train u(t) of eq. 3 (Heaviside step taken as 1 at 0);
+ * kind 2: the smoothed switching v(t) of eq. 4.  pp = t_per, t_src, t_trs,
+ * xi, zeta.  The sum over periods runs over every n from 0 up to the period
+ * after the one containing t (later periods contribute exactly nothing for
+ * t >= 0 in eq. 3, and at most the far tail of the erf in eq. 4).
+ */
+double or_pulse(int kind, double t, const double *pp) {
+  if (kind == 0) return 1.0;
+  const double tper = pp[0], tsrc = pp[1], ttrs = pp[2], xi = pp[3], zeta = pp[4];
+  long nmax = (long)floor(t / tper) + 1;
+  double s = 0.0;
+  for (long n = 0; n <= nmax; ++n) {
+    double a = t - n * tper;       /* time since the n-th switch-on */
+    double b = t - n * tper - tsrc; /* time since the n-th switch-off */
+    if (kind == 1) {
+      s += (a >= 0.0 ? 1.0 : 0.0) - (b >= 0.0 ? 1.0 : 0.0);
+    } else {
+      s += 0.5 * (erf(xi * (zeta * a / ttrs - 1.0)) - erf(xi * (zeta * b / ttrs - 1.0)));
+    }
+  }
+  return s;
+}
+
+/* Coefficients of A_r at row j, position i, with the laws evaluated on the
+ * field F (eq. 10 in balance form): A_r T = w T[i-1] + c T[i] + e T[i+1] + b. */
+static void nl_coef_r(const or_problem *p, const double *F, int j, int i,
+                      double *w, double *cc, double *e, double *b) {
+  int nr = p->nr;
+  size_t c = (size_t)j * nr + i;
+  int m = p->region[c];
+  double vol_r = p->rc[i] * p->dr[i];
+  double kc = poly3(p->lam[m], F[c]);
+  *w = 0.0; *cc = 0.0; *e = 0.0; *b = 0.0;
+  if (i == 0) {
+    /* axis: no flux */
+  } else if (p->region[c - 1] == OR_MASKED) {
+    double g = series_g(p->dr[i], kc, p->h[3]);
+    *cc -= p->rf[i] * g / vol_r;
+    *b += p->rf[i] * g * p->tinf[3] / vol_r;
+  } else {
+    double Tf = 0.5 * (F[c - 1] + F[c]);
+    double G = face_G(p->dr[i - 1], poly3(p->lam[p->region[c - 1]], Tf), p->dr[i], poly3(p->lam[m], Tf));
+    *w = p->rf[i] * G / vol_r;
+    *cc -= p->rf[i] * G / vol_r;
+  }
+  if (i == nr - 1 || p->region[c + 1] == OR_MASKED) {
+    int cls = (i == nr - 1) ? 1 : 3;
+    double g = series_g(p->dr[i], kc, p->h[cls]);
+    *cc -= p->rf[i + 1] * g / vol_r;
+    *b += p->rf[i + 1] * g * p->tinf[cls] / vol_r;
+  } else {
+    double Tf = 0.5 * (F[c] + F[c + 1]);
+    double G = face_G(p->dr[i], poly3(p->lam[m], Tf), p->dr[i + 1], poly3(p->lam[p->region[c + 1]], Tf));
+    *e = p->rf[i + 1] * G / vol_r;
+    *cc -= p->rf[i + 1] * G / vol_r;
+  }
+}
+
+/* Coefficients of A_z at row j, position i, laws on F (eq. 11):
+ * A_z T = s T[j-1] + c T[j] + n T[j+1] + b. */
+static void nl_coef_z(const or_problem *p, const double *F, int j, int i,
+                      double *so, double *cc, double *no, double *b) {
+  int nr = p->nr, nz = p->nz;
+  size_t c = (size_t)j * nr + i;
+  int m = p->region[c];
+  double kc = poly3(p->lam[m], F[c]);
+  *so = 0.0; *cc = 0.0; *no = 0.0; *b = 0.0;
+  if (j == 0 || p->region[c - nr] == OR_MASKED) {
+    int cls = (j == 0) ? 0 : 3;
+    double g = series_g(p->dz[j], kc, p->h[cls]);
+    *cc -= g / p->dz[j];
+    *b += g * p->tinf[cls] / p->dz[j];
+  } else {
+    double Tf = 0.5 * (F[c - nr] + F[c]);
+    double G = face_G(p->dz[j - 1], poly3(p->lam[p->region[c - nr]], Tf), p->dz[j], poly3(p->lam[m], Tf));
+    *so = G / p->dz[j];
+    *cc -= G / p->dz[j];
+  }
+  if (j == nz - 1 || p->region[c + nr] == OR_MASKED) {
+    int cls = (j == nz - 1) ? 2 : 3;
+    double g = series_g(p->dz[j], kc, p->h[cls]);
+    *cc -= g / p->dz[j];
+    *b += g * p->tinf[cls] / p->dz[j];
+  } else {
+    double Tf = 0.5 * (F[c] + F[c + nr]);
+    double G = face_G(p->dz[j], poly3(p->lam[m], Tf), p->dz[j + 1], poly3(p->lam[p->region[c + nr]], Tf));
+    *no = G / p->dz[j];
+    *cc -= G / p->dz[j];
+  }
+}
+
+/* (A_r T) and (A_z T) with the laws evaluated on the field F, boundary
+ * constants included (0 outside the domain). */
+void or_nl_apply(const or_problem *p, const double *F, const double *T, double *Ar, double *Az) {
+  int nr = p->nr, nz = p->nz;
+  for (int j = 0; j < nz; ++j)
+    for (int i = 0; i < nr; ++i) {
+      size_t c = (size_t)j * nr + i;
+      if (p->region[c] == OR_MASKED) { Ar[c] = 0.0; Az[c] = 0.0; continue; }
+      double w, cc, e, b;
+      nl_coef_r(p, F, j, i, &w, &cc, &e, &b);
+      double v = cc * T[c] + b;
+      if (i > 0) v += w * T[c - 1];
+      if (i < nr - 1) v += e * T[c + 1];
+      Ar[c] = v;
+      nl_coef_z(p, F, j, i, &w, &cc, &e, &b);
+      v = cc * T[c] + b;
+      if (j > 0) v += w * T[c - nr];
+      if (j < nz - 1) v += e * T[c + nr];
+      Az[c] = v;
+    }
+}
+
+/* Largest |a - b| over the cells of the domain (the norm of eq. 13). */
+static double max_change(const or_problem *p, const double *a, const double *b) {
+  double d = 0.0;
+  size_t n = (size_t)p->nr * p->nz;
+  for (size_t c = 0; c < n; ++c) {
+    if (p->region[c] == OR_MASKED) continue;
+    double x = fabs(a[c] - b[c]);
+    if (x > d) d = x;
+  }
+  return d;
+}
+
+/*
+ * First half step by the iteration of eq. 12: implicit in r with the laws
+ * at the iterate T^s, explicit Lambda_z at the current layer T (laws at T).
+ * Tbar receives the last iterate.  Returns the number of solves if the stop
+ * rule of eq. 13 was met within iter_max, else -1 (Tbar then holds the last
+ * iterate).  work: 2 fields.  *last_change: the norm that decided.
+ */
+static int nl_half_r(const or_problem *p, const double *T, double ta, double pval,
+                     double eps, int iter_max, double *Tbar, double *work,
+                     or_lines *w, double *last_change) {
+  int nr = p->nr, nz = p->nz;
+  size_t n = (size_t)nr * nz;
+  double *Ts = work, *Az = work + n;
+  /* the explicit part Lambda_z[T] does not change over the iteration */
+  for (int j = 0; j < nz; ++j)
+    for (int i = 0; i < nr; ++i) {
+      size_t c = (size_t)j * nr + i;
+      if (p->region[c] == OR_MASKED) { Az[c] = 0.0; continue; }
+      double so, cc, no, b;
+      nl_coef_z(p, T, j, i, &so, &cc, &no, &b);
+      double az = cc * T[c] + b;
+      if (j > 0) az += so * T[c - nr];
+      if (j < nz - 1) az += no * T[c + nr];
+      Az[c] = az;
+    }
+  memcpy(Ts, T, sizeof(double) * n);                       /* T^0 = T */
+  for (int s = 0; s < iter_max; ++s) {
+    for (int j = 0; j < nz; ++j) {
+      for (int i = 0; i < nr; ++i) {
+        size_t c = (size_t)j * nr + i;
+        int m = p->region[c];
+        if (m == OR_MASKED) {
+          w->a[i] = 0.0; w->b[i] = 1.0; w->c[i] = 0.0; w->d[i] = 0.0;
+          continue;
+        }
+        double we, cc, ea, b;
+        nl_coef_r(p, Ts, j, i, &we, &cc, &ea, &b);
+        double Cc = poly3(p->cap[m], Ts[c]) / ta;
+        double X = poly3(p->src[m], Ts[c]) * pval;
+        w->a[i] = -we;
+        w->b[i] = Cc - cc;
+        w->c[i] = -ea;
+        w->d[i] = Cc * T[c] + Az[c] + X + b;
+      }
+      or_thomas(nr, w->a, w->b, w->c, w->d, w->x, w->cp, w->dp);
+      for (int i = 0; i < nr; ++i) Tbar[(size_t)j * nr + i] = w->x[i];
+    }
+    double d = max_change(p, Tbar, Ts);
+    *last_change = d;
+    if (d < eps) return s + 1;
+    memcpy(Ts, Tbar, sizeof(double) * n);
+  }
+  return -1;
+}
+
+/*
+ * Second half step by the iteration of eq. 14: implicit in z with the laws
+ * at the iterate, rho c_V and the source at T-bar, explicit Lambda_r[T-bar]
+ * (laws at T-bar).  Same conventions as nl_half_r.
+ */
+static int nl_half_z(const or_problem *p, const double *Tbar, double ta, double pval,
+                     double eps, int iter_max, double *That, double *work,
+                     or_lines *w, double *last_change) {
+  int nr = p->nr, nz = p->nz;
+  size_t n = (size_t)nr * nz;
+  double *Ts = work, *Ar = work + n;
+  for (int j = 0; j < nz; ++j)
+    for (int i = 0; i < nr; ++i) {
+      size_t c = (size_t)j * nr + i;
+      int m = p->region[c];
+      if (m == OR_MASKED) { Ar[c] = 0.0; continue; }
+      double we, cc, ea, b;
+      nl_coef_r(p, Tbar, j, i, &we, &cc, &ea, &b);
+      double ar = cc * Tbar[c] + b;
+      if (i > 0) ar += we * Tbar[c - 1];
+      if (i < nr - 1) ar += ea * Tbar[c + 1];
+      Ar[c] = ar + poly3(p->src[m], Tbar[c]) * pval;   /* Lambda_r[T-bar] + X-bar */
+    }
+  memcpy(Ts, Tbar, sizeof(double) * n);                    /* T^0 = T-bar */
+  for (int s = 0; s < iter_max; ++s) {
+    for (int i = 0; i < nr; ++i) {
+      for (int j = 0; j < nz; ++j) {
+        size_t c = (size_t)j * nr + i;
+        int m = p->region[c];
+        if (m == OR_MASKED) {
+          w->a[j] = 0.0; w->b[j] = 1.0; w->c[j] = 0.0; w->d[j] = 0.0;
+          continue;
+        }
+        double so, cc, no, b;
+        nl_coef_z(p, Ts, j, i, &so, &cc, &no, &b);
+        double Cc = poly3(p->cap[m], Tbar[c]) / ta;
+        w->a[j] = -so;
+        w->b[j] = Cc - cc;
+        w->c[j] = -no;
+        w->d[j] = Cc * Tbar[c] + Ar[c] + b;
+      }
+      or_thomas(nz, w->a, w->b, w->c, w->d, w->x, w->cp, w->dp);
+      for (int j = 0; j < nz; ++j) That[(size_t)j * nr + i] = w->x[j];
+    }
+    double d = max_change(p, That, Ts);
+    *last_change = d;
+    if (d < eps) return s + 1;
+    memcpy(Ts, That, sizeof(double) * n);
+  }
+  return -1;
+}
+
+/*
+ * One step of size tau from time t by eq. 12 then eq. 14 (Peaceman-
+ * Rachford half steps of tau/2, source at t + tau/2).  On success T is
+ * replaced by T-hat and 1 is returned; if either iteration fails to stop
+ * within iter_max solves, T is left unchanged and 0 is returned.  it[0],
+ * it[1] receive the solves of each half step (-1: failed, 0: not run);
+ * chg[0], chg[1] the last change norm of each (the value compared with eps).
+ */
+int or_nl_step(const or_problem *p, double *T, double tau, double t, int kind, const double *pp,
+               double eps, int iter_max, int *it, double *chg) {
+  size_t n = (size_t)p->nr * p->nz;
+  int L = p->nr > p->nz ? p->nr : p->nz;
+  double ta = 0.5 * tau;
+  double pval = or_pulse(kind, t + 0.5 * tau, pp);
+  or_lines w;
+  double *buf = malloc(sizeof(double) * 4 * n);
+  if (!buf || !lines_alloc(&w, L)) { free(buf); lines_free(&w); return OR_ENOMEM; }
+  double *Tbar = buf, *That = buf + n, *work = buf + 2 * n;
+  it[0] = it[1] = 0;
+  chg[0] = chg[1] = 0.0;
+  int ok = 0;
+  it[0] = nl_half_r(p, T, ta, pval, eps, iter_max, Tbar, work, &w, &chg[0]);
+  if (it[0] > 0) {
+    it[1] = nl_half_z(p, Tbar, ta, pval, eps, iter_max, That, work, &w, &chg[1]);
+    if (it[1] > 0) {
+      memcpy(T, That, sizeof(double) * n);
+      ok = 1;
+    }
+  }
+  free(buf);
+  lines_free(&w);
+  return ok;
+}
+
+/* Switch points and transition ends of the source in the period of t and
+ * the next one: n t_per, n t_per + t_trs, n t_per + t_src, n t_per + t_src
+ * + t_trs.  Returns the first one later than t + guard (or +inf). */
+static double next_boundary(double t, const double *pp, double guard) {
+  const double tper = pp[0], tsrc = pp[1], ttrs = pp[2];
+  double n0 = floor(t / tper);
+  double best = INFINITY;
+  for (int k = 0; k < 2; ++k) {
+    double base = (n0 + k) * tper;
+    double cand[4] = {base, base + ttrs, base + tsrc, base + tsrc + ttrs};
+    for (int q = 0; q < 4; ++q)
+      if (cand[q] > t + guard && cand[q] < best) best = cand[q];
+  }
+  return best;
+}
+
+/* Inside a transition: the first t_trs after a switch-on or a switch-off. */
+static int in_transition(double t, const double *pp) {
+  const double tper = pp[0], tsrc = pp[1], ttrs = pp[2];
+  double ph = t - floor(t / tper) * tper;
+  return ph < ttrs || (ph >= tsrc && ph < tsrc + ttrs);
+}
+
+/*
+ * The adaptive loop of Sec. 4 from time *t up to t_end (or the periodic
+ * regime).  kind / pp: the source pulse (pp = t_per, t_src, t_trs, xi,
+ * zeta); with kind 0 (constant source) the step is t_src/100 throughout
+ * and no boundaries are placed.  ctl = eps, tau_min, periodic_tol (0: no
+ * periodic stop), tau_trs_div (1000), tau_src_div (100); iter_max the
+ * iteration limit; max_steps a cap on accepted steps.
+ * counts[0..4] receive: accepted steps, rejected (halved) attempts, solves
+ * of the r iterations, solves of the z iterations, periodic stop flag.
+ * If log is not NULL, up to log_cap accepted steps are recorded as
+ * (t_before, tau, solves_r, solves_z).  *t is advanced.  Returns OR_OK, or
+ * OR_EINVAL when tau fell below tau_min.
+ */
+int or_nl_run(const or_problem *p, double *T, double *t, double t_end, int kind, const double *pp,
+              const double *ctl, int iter_max, long max_steps, long *counts, double *log, long log_cap,
+              double *min_margin) {
+  const double eps = ctl[0], tau_min = ctl[1], ptol = ctl[2];
+  const double div_trs = ctl[3], div_src = ctl[4];
+  size_t n = (size_t)p->nr * p->nz;
+  double *prev = malloc(sizeof(double) * n);
+  if (!prev) return OR_ENOMEM;
+  memcpy(prev, T, sizeof(double) * n);
+  for (int q = 0; q < 5; ++q) counts[q] = 0;
+  double margin = INFINITY;
+  int status = OR_OK;
+  /* times closer than this to a switch point or transition end count as
+   * being on it (t accumulates rounding as it steps) */
+  const double guard = 1e-9 * pp[2] / div_trs;
+  while (counts[0] < max_steps) {
+    if (!(t_end - *t > guard)) break;
+    double tau0 = (kind != 0 && in_transition(*t + guard, pp)) ? pp[2] / div_trs : pp[1] / div_src;
+    double tau = tau0;
+    int ends_period = 0;
+    if (kind != 0) {
+      double b = next_boundary(*t, pp, guard);
+      if (b - *t <= tau) {
+        tau = b - *t;
+        /* landing on a period start: b is a multiple of t_per */
+        double k = floor(b / pp[0] + 0.5);
+        ends_period = fabs(b - k * pp[0]) <= guard;
+      }
+    }
+    if (t_end - *t < tau) { tau = t_end - *t; ends_period = 0; }
+    int it[2];
+    double chg[2];
+    for (;;) {
+      int ok = or_nl_step(p, T, tau, *t, kind, pp, eps, iter_max, it, chg);
+      if (ok < 0) { status = ok; goto done; }
+      for (int h = 0; h < 2; ++h)
+        if (it[h] != 0) {
+          double mg = fabs(chg[h] - eps) / eps;
+          if (mg < margin) margin = mg;
+        }
+      if (ok) break;
+      counts[1] += 1;
+      tau *= 0.5;
+      ends_period = 0;
+      if (tau < tau_min) { status = OR_EINVAL; goto done; }
+    }
+    if (log && counts[0] < log_cap) {
+      double *r = log + 4 * counts[0];
+      r[0] = *t; r[1] = tau; r[2] = it[0]; r[3] = it[1];
+    }
+    *t += tau;
+    counts[0] += 1;
+    counts[2] += it[0];
+    counts[3] += it[1];
+    if (ends_period && ptol > 0.0) {
+      double d = max_change(p, T, prev);
+      double mg = fabs(d - ptol) / ptol;
+      if (mg < margin) margin = mg;
+      memcpy(prev, T, sizeof(double) * n);
+      if (d < ptol) { counts[4] = 1; break; }
+    }
+  }
+done:
+  if (min_margin) *min_margin = margin;
+  free(prev);
+  return status;
 }
