@@ -326,6 +326,22 @@ adi_status adi_mlp_gradients(adi_mlp m, const float* dev_x, const float* dev_t, 
 adi_status adi_mlp_train_step(adi_mlp m, const float* dev_x, const float* dev_t, int64_t batch, float lr,
                               float* loss_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * network output as adi_mlp_forward (bit for bit: the same products and
+ * epilogues), with the encoded input and the hidden activations kept in a
+ * fixed work area of ADI_MLP_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, and the output written
+ * straight into dev_y.  Allocates nothing.  The area takes
+ * 2 * batch * (64 + 2 * w) bytes, w the widest hidden layer (at most 14,528
+ * rows for 256-wide layers): larger batches fail with ADI_EINVAL.  Every
+ * call on one GPU uses the same area: calls ordered on one stream are safe,
+ * calls that overlap in time on one GPU (other streams or threads) race.
+ * Asynchronous on the network's stream; the inputs and dev_y must stay
+ * allocated until that work has finished. */
+#define ADI_MLP_NOALLOC_SCRATCH_BYTES (16u << 20)
+adi_status adi_mlp_forward_noalloc(adi_mlp m, const float* dev_x, int64_t batch, float* dev_y);
+
 void adi_mlp_destroy(adi_mlp m);
 
 /* ---------------------------------------------------------- utilities -- */

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -27,7 +28,9 @@ constexpr int BM = 64, BN = 64, KT = 32, LDP = KT + 8;  // tile sizes; padded LD
 constexpr int MAX_LAYERS = 8;
 constexpr int KPAD = 64;                                 // input features padded to a whole tile
 
-enum Epi { EPI_HIDDEN = 0, EPI_OUTPUT = 1, EPI_DGELU = 2, EPI_PARTIAL = 3 };
+// EPI_INFER: the hidden epilogue without the fp32 pre-activation (inference
+// only, nothing kept for a backward pass).
+enum Epi { EPI_HIDDEN = 0, EPI_OUTPUT = 1, EPI_DGELU = 2, EPI_PARTIAL = 3, EPI_INFER = 4 };
 
 struct GemmArgs {
   const __bf16* A;  // [M][K] (a_kmajor) or [K][M]
@@ -101,9 +104,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     const int m = m0 + wm + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
     const long o = (long)m * g.ldo + n;
     const float v = acc[i];
-    if constexpr (EPI == EPI_HIDDEN) {
+    if constexpr (EPI == EPI_HIDDEN || EPI == EPI_INFER) {
       const float u = v + g.bias[n];
-      g.out_f32[o] = u;
+      if constexpr (EPI == EPI_HIDDEN) g.out_f32[o] = u;
       g.out_bf16[o] = (__bf16)gelu_f(u);
     } else if constexpr (EPI == EPI_OUTPUT) {
       g.out_f32[o] = v + g.bias[n];
@@ -210,7 +213,42 @@ __global__ void k_refresh(const float* __restrict__ W, int kin, int kin_pad, int
 
 }  // namespace adi
 
+// Work area of adi_mlp_forward_noalloc: the encoded input and two ping-pong
+// hidden activations (bf16), for callers that cannot allocate.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// symbol): it uses the device address obtained once per device with
+// hipGetSymbolAddress (noalloc_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[ADI_MLP_NOALLOC_SCRATCH_BYTES];
+
 using namespace adi;
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device `dev`, looked up once per
+// device (called with that device current).
+adi_status noalloc_scratch_setup(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(ADI_EUNSUPPORTED, "device %d beyond %d", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return ADI_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(ADI_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  return ADI_OK;
+}
+
+void* noalloc_scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (dev >= 0 && dev < MAX_DEVICES) ? g_scratch_ptr[dev] : nullptr;
+}
+
+}  // namespace
 
 struct adi_mlp_s {
   int device = 0;
@@ -313,6 +351,38 @@ adi_status check_batch(adi_mlp m, long B) {
   if (B < 1 || B > (1L << 26)) return fail(ADI_EINVAL, "batch must be in [1, 2^26]");
   if (B % BM) return fail(ADI_EINVAL, "batch must be a multiple of %d", BM);
   (void)m;
+  return ADI_OK;
+}
+
+// Inference-only forward pass: encoded input in X, hidden activations
+// alternating between H0 and H1 (no pre-activations kept), output straight
+// into y.  The same products and epilogue arithmetic as forward().
+adi_status forward_infer(adi_mlp m, const float* x, long B, __bf16* X, __bf16* H0, __bf16* H1, float* y) {
+  hipLaunchKernelGGL(k_encode, dim3((int)std::min<long>((B * KPAD + 255) / 256, 8192)), dim3(256), 0, m->stream,
+                     x, m->width[0], B, m->shift, m->scale, X);
+  ADI_CHECK_LAUNCH();
+  const __bf16* in = X;
+  for (int l = 0; l < m->nl; ++l) {
+    GemmArgs g{};
+    g.A = in;
+    g.lda = m->kin_pad[l];
+    g.B = m->Wtb[l];
+    g.ldb = m->kin_pad[l];
+    g.M = (int)B;
+    g.N = m->width[l + 1];
+    g.K = g.Ks = m->kin_pad[l];
+    g.bias = m->P + m->boff[l];
+    g.ldo = m->width[l + 1];
+    if (l < m->nl - 1) {
+      __bf16* out = (l & 1) ? H1 : H0;
+      g.out_bf16 = out;
+      ADI_TRY((gemm<true, true, EPI_INFER>(m, g, 1)));
+      in = out;
+    } else {
+      g.out_f32 = y;
+      ADI_TRY((gemm<true, true, EPI_OUTPUT>(m, g, 1)));
+    }
+  }
   return ADI_OK;
 }
 
@@ -445,13 +515,14 @@ adi_status adi_mlp_create(const int32_t* widths, int32_t nwidths, uint64_t seed,
   m->nparams = off;
   hipError_t e = hipGetDevice(&m->device);
   if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+  adi_status st = noalloc_scratch_setup(m->device);
+  if (st != ADI_OK) return cleanup(st);
   m->stream = (hipStream_t)hip_stream;
   if (!m->stream) {
     e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
     m->own_stream = true;
   }
-  adi_status st;
   float** f32[] = {&m->P, &m->Gr, &m->Mm, &m->Vv};
   for (float** p : f32)
     if ((st = dev_alloc((void**)p, 4 * m->nparams, m->stream)) != ADI_OK) return cleanup(st);
@@ -534,6 +605,25 @@ adi_status adi_mlp_forward(adi_mlp m, const float* dev_x, int64_t batch, float* 
   ADI_TRY(forward(m, dev_x, batch));
   ADI_HIP(hipMemcpyAsync(dev_y, m->Y, 4 * batch * m->width[m->nl], hipMemcpyDeviceToDevice, m->stream));
   return ADI_OK;
+}
+
+adi_status adi_mlp_forward_noalloc(adi_mlp m, const float* dev_x, int64_t batch, float* dev_y) {
+  ADI_TRY(mlp_handle(m));
+  if (!dev_x || !dev_y) return fail(ADI_EINVAL, "null device buffer");
+  ADI_TRY(check_batch(m, batch));
+  int wmax = 0;
+  for (int l = 1; l < m->nl; ++l) wmax = std::max(wmax, m->width[l]);
+  // X: batch x KPAD, H0 and H1: batch x wmax (bf16); batch is a multiple of
+  // 64 and the widths multiples of 64, so every part starts 256-byte aligned
+  const long xb = 2L * batch * KPAD, hb = 2L * batch * wmax;
+  const long per_row = 2L * (KPAD + 2L * wmax);
+  if (xb + 2 * hb > (long)ADI_MLP_NOALLOC_SCRATCH_BYTES)
+    return fail(ADI_EINVAL, "batch %ld needs %ld bytes of work area, more than the %ld available (at most %ld rows "
+                "for this network)", (long)batch, xb + 2 * hb, (long)ADI_MLP_NOALLOC_SCRATCH_BYTES,
+                (long)ADI_MLP_NOALLOC_SCRATCH_BYTES / per_row / BM * BM);
+  unsigned char* base = (unsigned char*)noalloc_scratch_ptr(m->device);
+  if (!base) return fail(ADI_EDEVICE, "work area of device %d was not set up", m->device);
+  return forward_infer(m, dev_x, batch, (__bf16*)base, (__bf16*)(base + xb), (__bf16*)(base + xb + hb), dev_y);
 }
 
 adi_status adi_mlp_sync(adi_mlp m) {

@@ -111,6 +111,7 @@ _SIGS = {
     "adi_mlp_get_params": [_vp, _fp, ctypes.c_int64],
     "adi_mlp_set_params": [_vp, _fp, ctypes.c_int64],
     "adi_mlp_forward": [_vp, _vp, ctypes.c_int64, _vp],
+    "adi_mlp_forward_noalloc": [_vp, _vp, ctypes.c_int64, _vp],
     "adi_mlp_gradients": [_vp, _vp, _vp, ctypes.c_int64, _fp, _fp],
     "adi_mlp_train_step": [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _fp],
     "adi_mlp_destroy": [_vp],
@@ -488,6 +489,14 @@ class MLP:
         self._before()
         check(lib().adi_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
                                     ctypes.c_void_p(y.data_ptr())))
+        self._after()
+
+    def forward_noalloc(self, x, y):
+        """forward() through adi_mlp_forward_noalloc: the activations live in
+        the library's fixed per-GPU work area, nothing is allocated."""
+        self._before()
+        check(lib().adi_mlp_forward_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                            ctypes.c_void_p(y.data_ptr())))
         self._after()
 
     def gradients(self, x, t):
