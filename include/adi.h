@@ -205,6 +205,84 @@ adi_status adi_set_graph_steps(adi_problem p, int32_t steps);
 
 void adi_destroy(adi_problem p);
 
+/* ---------------------------------------------- nonlinear method path -- */
+
+/* The paper's method with temperature-dependent coefficients (Sec. 2-4):
+ * lambda(T), rho c_V(T) and the source amplitude chi(T) I^2/S_C per region,
+ * each half step of eq. 8-9 solved by the simple iteration of eq. 12 (r
+ * implicit, laws and source at the iterate, Lambda_z at the current layer)
+ * and eq. 14 (z implicit, laws at the iterate, rho c_V, Lambda_r and the
+ * source at T-bar), stopped by the max-norm rule of eq. 13
+ * (max |T^{s+1} - T^s| over the cells of the domain < eps); a half step that
+ * has not stopped after iter_max solves fails, and the step is retried from
+ * the same T with tau/2 (end of Sec. 3).  Face conductivities take each
+ * side's lambda at the mean of the two cell temperatures and combine the
+ * half cells in series; a film uses lambda at the cell's own temperature.
+ * The source of both half steps is evaluated at t + tau/2 through the pulse
+ * p(t) of eq. 2-4.  These calls use the problem's geometry, films and field;
+ * the constant materials and sources of adi_set_materials / adi_set_sources
+ * do not enter.  Lines of at most 3072 cells (ADI_EUNSUPPORTED otherwise). */
+
+/* Laws per region (5 regions x 4 coefficients, region-major): value =
+ * c0 + c1 T + c2 T^2 + c3 T^3.  lam: conductivity, cap: volumetric heat
+ * capacity, src: source amplitude.  Finite coefficients (ADI_ENONFINITE);
+ * the laws must stay positive (lam, cap) over the temperatures reached. */
+adi_status adi_set_laws(adi_problem p, const double lam[20], const double cap[20], const double src[20]);
+
+/* Normalised source p(t) (eq. 2): kind 0 constant 1; kind 1 the rectangular
+ * pulse train of eq. 3; kind 2 the erf-smoothed switching of eq. 4.  params:
+ * t_per, t_src, t_trs, xi, zeta with 0 < t_trs <= t_src, t_src + t_trs <=
+ * t_per, zeta > 0 (kind 0: only t_src, t_trs > 0 are checked; the step rule
+ * of adi_set_step_rule reads t_src and t_trs for every kind); NULL allowed
+ * for kind 0 (keeps the previous values, initially 0.1, 0.01, 1e-4, 4, 2). */
+adi_status adi_set_pulse(adi_problem p, int32_t kind, const double params[5]);
+
+/* Stop rule and retries: eps > 0 of eq. 13, iter_max in [1, 64] solves per
+ * half step, tau_min > 0 (a run fails once halving goes below it).
+ * Defaults 1e-6, 10, 1e-12. */
+adi_status adi_set_iteration(adi_problem p, double eps, int32_t iter_max, double tau_min);
+
+/* Step rule of Sec. 4: each step starts with tau = t_trs/tau_trs_div inside
+ * a transition of the source (the first t_trs after a switch-on or a
+ * switch-off) and t_src/tau_src_div elsewhere, and ends no later than the
+ * next switch point, transition end or t_end (constant source: t_src/
+ * tau_src_div throughout).  periodic_tol > 0: at every period start the
+ * field is compared with the previous period start's, and the run stops
+ * once the max-norm change is below periodic_tol (0: never).  Defaults
+ * 1000, 100, 0. */
+adi_status adi_set_step_rule(adi_problem p, double tau_trs_div, double tau_src_div, double periodic_tol);
+
+/* One step attempt of size tau from the problem's current time, without
+ * the step rule and without halving.  *accepted (nullable): 1 if both
+ * iterations stopped (the field and time then advance), else 0 (the field
+ * is unchanged).  solves (nullable, 2): solves of each half step (-1: did
+ * not stop, 0: not run).  changes (nullable, 2): the change norm that
+ * decided each half.  Synchronises.  ADI_ESTATE before adi_set_laws. */
+adi_status adi_nl_step(adi_problem p, double tau, int32_t* accepted, int32_t solves[2], double changes[2]);
+
+typedef struct {
+  double t;            /* model time reached */
+  int64_t steps;       /* accepted steps */
+  int64_t rejected;    /* attempts retried with half the step */
+  int64_t solves_r;    /* line-system solves of the r half steps (accepted steps) */
+  int64_t solves_z;    /* same for the z half steps */
+  int32_t periodic;    /* 1 if the periodic-regime stop ended the run */
+  double min_margin;   /* smallest |change - bound| / bound over every stop
+                          decision (eq. 13 and periodic): how far the run's
+                          decisions were from a tie */
+} adi_nl_report;
+
+/* The time loop of Sec. 4 from the problem's current time up to t_end (or
+ * the periodic stop, or max_steps accepted steps), on the device in one
+ * persistent cooperative kernel per 4096 attempts.  host_log (nullable,
+ * 4*log_cap doubles): (t before, tau, solves_r, solves_z) of the first
+ * log_cap accepted steps.  out (nullable) receives the report.
+ * Synchronises.  ADI_EINVAL if halving went below tau_min (the field then
+ * holds the last accepted step), ADI_EDEVICE if a grid-wide wait of the
+ * kernel ran out. */
+adi_status adi_nl_run(adi_problem p, double t_end, int64_t max_steps, double* host_log, int64_t log_cap,
+                      adi_nl_report* out);
+
 /* ------------------------------------------------------- ragged batch -- */
 
 /* A batch of n independent instances (the design sweep): instance i has its

@@ -21,6 +21,7 @@
 #include "common.hpp"
 #include "device.hpp"
 #include "strip.hpp"
+#include "problem_core.hpp"
 
 namespace adi {
 
@@ -540,6 +541,9 @@ struct adi_problem_s {
     hipGraphExec_t exec;
   };
   std::vector<Seg> graphs;
+  // extension state (the nonlinear path) and its destructor
+  void* ext = nullptr;
+  void (*ext_destroy)(void*) = nullptr;
 };
 
 namespace {
@@ -844,6 +848,37 @@ adi_status validate_bc(const adi_bc* bc) {
 }  // namespace
 
 // ------------------------------------------------------------------ ABI --
+
+namespace adi {
+
+adi_status problem_core(adi_problem p, ProblemCore* out) {
+  ADI_TRY(check_handle(p));
+  if (!out) return fail(ADI_EINVAL, "null output");
+  ADI_TRY(build_geometry_once(p));
+  out->device = p->device;
+  out->stream = p->stream;
+  out->P = p->P;
+  out->g = p->g;
+  out->T = p->T;
+  out->time = p->time;
+  return ADI_OK;
+}
+
+void problem_field_advanced(adi_problem p, double time, int64_t steps) {
+  p->rhs_valid = false;
+  p->time = time;
+  p->steps += steps;
+}
+
+void* problem_ext(adi_problem p) { return p ? p->ext : nullptr; }
+
+void problem_set_ext(adi_problem p, void* ext, void (*destroy)(void*)) {
+  if (p->ext && p->ext_destroy && p->ext != ext) p->ext_destroy(p->ext);
+  p->ext = ext;
+  p->ext_destroy = destroy;
+}
+
+}  // namespace adi
 
 extern "C" {
 
@@ -1310,6 +1345,8 @@ void adi_destroy(adi_problem p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   drop_graphs(p);
+  if (p->ext && p->ext_destroy) p->ext_destroy(p->ext);
+  p->ext = nullptr;
   void* bufs[] = {p->d_rfi, p->d_zfi, p->geom_mem, p->tab_mem, p->T, p->dA, p->dB, p->mid,
                   p->part, p->eout, p->state, p->prof, p->dmap, p->dranges};
   for (void* b : bufs) dev_free(b);

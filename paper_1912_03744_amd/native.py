@@ -50,6 +50,12 @@ class BC(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double * 4), ("t_inf", ctypes.c_double * 4)]
 
 
+class NlReport(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("solves_r", ctypes.c_int64), ("solves_z", ctypes.c_int64), ("periodic", ctypes.c_int32),
+                ("min_margin", ctypes.c_double)]
+
+
 class EnergyReport(ctypes.Structure):
     _fields_ = [("E", ctypes.c_double), ("E0", ctypes.c_double), ("source_power", ctypes.c_double),
                 ("boundary_flow", ctypes.c_double), ("residual", ctypes.c_double),
@@ -89,6 +95,12 @@ _SIGS = {
     "adi_layout_shapes": [ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int32, _i32p],
     "adi_set_layout": [_vp, ctypes.c_int32],
     "adi_sync": [_vp],
+    "adi_set_laws": [_vp, _dp, _dp, _dp],
+    "adi_set_pulse": [_vp, ctypes.c_int32, _dp],
+    "adi_set_iteration": [_vp, ctypes.c_double, ctypes.c_int32, ctypes.c_double],
+    "adi_set_step_rule": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "adi_nl_step": [_vp, ctypes.c_double, _i32p, _i32p, _dp],
+    "adi_nl_run": [_vp, ctypes.c_double, ctypes.c_int64, _dp, ctypes.c_int64, ctypes.POINTER(NlReport)],
     "adi_mlp_sync": [_vp],
     "adi_get_layout": [_vp, _i32p],
     "adi_destroy": [_vp],
@@ -307,6 +319,45 @@ class Problem:
         v = [ctypes.c_int32() for _ in range(5)]
         check(lib().adi_get_launch(self._h, int(direction), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
+
+    # ---- nonlinear path (laws in T, simple iteration, pulsed source) ----
+    PULSES = {"const": 0, "rect": 1, "erf": 2}
+
+    def set_laws(self, lam, cap, src):
+        """5 x 4 polynomial coefficients per law (region-major)."""
+        self._laws = [_f64(lam, 20), _f64(cap, 20), _f64(src, 20)]
+        check(lib().adi_set_laws(self._h, *(_ptr(a) for a in self._laws)))
+
+    def set_pulse(self, kind, t_per=0.1, t_src=0.01, t_trs=1e-4, xi=4.0, zeta=2.0):
+        pp = _f64([t_per, t_src, t_trs, xi, zeta], 5)
+        check(lib().adi_set_pulse(self._h, self.PULSES[kind], _ptr(pp)))
+
+    def set_iteration(self, eps=1e-6, iter_max=10, tau_min=1e-12):
+        check(lib().adi_set_iteration(self._h, float(eps), int(iter_max), float(tau_min)))
+
+    def set_step_rule(self, tau_trs_div=1000.0, tau_src_div=100.0, periodic_tol=0.0):
+        check(lib().adi_set_step_rule(self._h, float(tau_trs_div), float(tau_src_div), float(periodic_tol)))
+
+    def nl_step(self, tau):
+        """One attempt of size tau: (accepted, (solves_r, solves_z), changes)."""
+        acc = ctypes.c_int32()
+        it = (ctypes.c_int32 * 2)()
+        chg = np.zeros(2)
+        check(lib().adi_nl_step(self._h, float(tau), ctypes.byref(acc), it, _ptr(chg)))
+        return bool(acc.value), (it[0], it[1]), chg
+
+    def nl_run(self, t_end, max_steps=1 << 62, log_cap=0):
+        """The adaptive loop up to t_end; returns the report as a dict (and
+        the per-step log rows when log_cap > 0)."""
+        rep = NlReport()
+        log = np.zeros((max(log_cap, 1), 4))
+        check(lib().adi_nl_run(self._h, float(t_end), int(max_steps), _ptr(log) if log_cap else None,
+                               int(log_cap), ctypes.byref(rep)))
+        out = {k: getattr(rep, k) for k, _ in NlReport._fields_}
+        out["periodic"] = bool(out["periodic"])
+        if log_cap:
+            out["log"] = log[:min(rep.steps, log_cap)]
+        return out
 
     def set_layout(self, layout):
         """"rows" or "strips" (adi_set_layout); resets the launch shapes."""

@@ -170,3 +170,55 @@ def layer_aligned_faces(bounds, counts):
     f = np.array(faces, dtype=np.float64)
     f[-1] = bounds[-1]
     return f
+
+
+# Sec. 5 case study: cell size, per-layer cell counts and source timing.
+CASE_STUDY_GEOM = dict(r0=0.24, r1=0.245, r2=0.25, rmax=0.2501, z0=4.0, zmax=5.0)
+CASE_STUDY_CELLS_R = (800, 200, 200, 10)   # core, insulator, heater, coating
+CASE_STUDY_CELLS_Z = (80, 20)              # up to z0 (all layers), z0 to zmax (core only)
+CASE_STUDY_PULSE = (0.1, 0.01, 1e-4, 4.0, 2.0)   # t_per, t_src, t_trs, xi, zeta
+CASE_STUDY_T0 = 4.2
+
+
+def case_study(scale_r=1.0, scale_z=1.0) -> Spec:
+    """The cell of Sec. 5 on its per-layer grid: r faces uniform inside each
+    layer (800, 200, 200, 10 cells; widths 3e-4, 2.5e-5, 2.5e-5, 1e-5), z
+    faces uniform with 80 cells up to z0 and 20 from z0 to zmax (0.05 each),
+    1210 x 100 cells.  No terminal slab (ztop = zmax): the terminal is the top
+    face of the core, held at T0 = 4.2 (Dirichlet, eq. 6); every other face
+    is insulated.  scale_r / scale_z shrink the cell counts of every layer
+    (at least 2 cells each) for smaller test grids.  The materials here are
+    placeholders: the nonlinear path takes its laws from case_study_laws."""
+    g = CASE_STUDY_GEOM
+    nrs = [max(2, int(round(c * scale_r))) for c in CASE_STUDY_CELLS_R]
+    nzs = [max(2, int(round(c * scale_z))) for c in CASE_STUDY_CELLS_Z]
+    rf = layer_aligned_faces((0.0, g["r0"], g["r1"], g["r2"], g["rmax"]), nrs)
+    zf = layer_aligned_faces((0.0, g["z0"], g["zmax"]), nzs)
+    return Spec(r0=g["r0"], r1=g["r1"], r2=g["r2"], rmax=g["rmax"], z0=g["z0"], zmax=g["zmax"], ztop=g["zmax"],
+                nr=len(rf) - 1, nz=len(zf) - 1, h=(0.0, 0.0, float("inf"), 0.0),
+                t_inf=(0.0, 0.0, CASE_STUDY_T0, 0.0), k=(40.0, 0.1, 1.0, 0.5, 1.0), rhoc=(1.0,) * 5,
+                q=(0.0, 0.0, 1.0, 0.0, 0.0), scheme="pr", dt=1e-4, T0=CASE_STUDY_T0, r_faces=rf, z_faces=zf)
+
+
+def case_study_laws():
+    """Synthetic temperature laws for the case study (the paper does not
+    publish its material data): per region (cooler, insulator, heater,
+    coating, terminal) cubic polynomials in T of the conductivity, the
+    volumetric heat capacity and the source amplitude, all positive and
+    increasing over 4 <= T <= 60: a copper-like core conducting 100x better
+    than the layers, capacities rising like a low-temperature solid's, and a
+    heater whose resistive source rises 1 % per unit of T.  Returns (lam,
+    cap, src) as 5 x 4 arrays (c0, c1, c2, c3)."""
+    lam = np.array([[40.0, 0.4, 0.0, 0.0],
+                    [0.1, 0.004, 0.0, 0.0],
+                    [1.0, 0.02, 0.0, 0.0],
+                    [0.5, 0.01, 0.0, 0.0],
+                    [40.0, 0.4, 0.0, 0.0]])
+    cap = np.array([[0.5, 0.0, 0.002, 2e-5],
+                    [0.8, 0.0, 0.003, 2e-5],
+                    [0.6, 0.0, 0.004, 3e-5],
+                    [0.7, 0.0, 0.003, 2e-5],
+                    [0.5, 0.0, 0.002, 2e-5]])
+    src = np.zeros((5, 4))
+    src[2] = (50000.0, 500.0, 0.0, 0.0)
+    return lam, cap, src

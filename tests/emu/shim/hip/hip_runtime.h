@@ -1,11 +1,15 @@
-// Host stand-in for the HIP device environment, for the CPU emulation test
-// of the strip-layout sweep kernels.  Every lane of a workgroup is a
-// user-level fiber (ucontext); a barrier is a yield to a round-robin
-// scheduler that resumes each lane in turn, so all lanes reach every barrier
-// before any passes it.  Workgroups run one after the other.  Wavefront
-// shuffles, DPP row operations and readlane are emulated through a slot per
-// lane and two barriers (all lanes execute them together, as on the
-// device).  Test infrastructure only: nothing in the library uses it.
+// Host stand-in for the HIP device environment, for the CPU emulation tests
+// of the library's kernels.  Every lane of a workgroup is a user-level fiber
+// (ucontext); a barrier is a yield to a round-robin scheduler that resumes
+// each lane in turn, so all lanes reach every barrier before any passes it.
+// emu_launch runs the workgroups one after the other; emu_launch_grid runs
+// them at the same time, one host thread each (for kernels that wait on each
+// other through device atomics; a wave's sleep yields the host thread).
+// Workgroup state (fibers, shared memory, thread and block indices) is per
+// host thread.  Wavefront shuffles, DPP row operations and readlane are
+// emulated through a slot per lane and two barriers (all lanes execute them
+// together, as on the device).  Test infrastructure only: nothing in the
+// library uses it.
 #pragma once
 #include <algorithm>
 #include <atomic>
@@ -14,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <ucontext.h>
 #include <vector>
 using std::max;
@@ -25,24 +30,25 @@ using std::min;
 #define __launch_bounds__(x)
 #define __restrict__
 #define __align__(x)
-#define __shared__ static
+#define __shared__ static thread_local
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
 #define __builtin_amdgcn_fence(a, b) std::atomic_thread_fence(std::memory_order_seq_cst)
 
 struct emu_dim3 {
   unsigned x = 0, y = 0, z = 0;
 };
-inline emu_dim3 threadIdx, blockIdx, gridDim, blockDim;
+inline thread_local emu_dim3 threadIdx, blockIdx;
+inline emu_dim3 gridDim, blockDim;
 
 // fiber scheduler
-inline ucontext_t emu_main_ctx;
-inline std::vector<ucontext_t> emu_lane_ctx;
-inline int emu_cur = 0;
+inline thread_local ucontext_t emu_main_ctx;
+inline thread_local std::vector<ucontext_t> emu_lane_ctx;
+inline thread_local int emu_cur = 0;
 inline void __syncthreads() { swapcontext(&emu_lane_ctx[emu_cur], &emu_main_ctx); }
 inline void __builtin_amdgcn_wave_barrier() { __syncthreads(); }
 
 // one exchange slot per lane; a value is published, then read from lane src
-inline long long emu_slot[1024];
+inline thread_local long long emu_slot[1024];
 inline long long emu_exchange(long long v, int src_lane_in_wave, bool valid, long long fallback) {
   const int l = threadIdx.x;
   emu_slot[l] = v;
@@ -119,6 +125,31 @@ inline int __builtin_amdgcn_mov_dpp(int src, int ctrl, int row_mask, int bank_ma
 }
 inline int __builtin_amdgcn_readlane(int v, int l) { return (int)emu_exchange(v, l, true, 0); }
 inline int atomicAdd(int* p, int v) { return reinterpret_cast<std::atomic<int>*>(p)->fetch_add(v); }
+inline unsigned atomicAdd(unsigned* p, unsigned v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned atomicExch(unsigned* p, unsigned v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
+inline int atomicExch(int* p, int v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned long long atomicMax(unsigned long long* p, unsigned long long v) {
+  unsigned long long o = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (o < v && !__atomic_compare_exchange_n(p, &o, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+  }
+  return o;
+}
+#define __HIP_MEMORY_SCOPE_AGENT 0
+template <class T>
+inline T __hip_atomic_load(T* p, int, int) { return __atomic_load_n(p, __ATOMIC_SEQ_CST); }
+inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
+inline int __shfl(int v, int src, int w = 64) { return (int)emu_exchange(v, src & 63, true, v); }
+inline double __shfl(double v, int src, int w = 64) {
+  return __longlong_as_double(emu_exchange(__double_as_longlong(v), src & 63, true, __double_as_longlong(v)));
+}
+inline double __shfl_xor(double v, int mask, int w = 64) {
+  const int lane = threadIdx.x & 63;
+  return __longlong_as_double(emu_exchange(__double_as_longlong(v), lane ^ mask, true, __double_as_longlong(v)));
+}
+// dynamic shared memory of the current workgroup (sized by the launch)
+inline thread_local std::vector<double> emu_dyn_lds;
+#define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(emu_dyn_lds.data());
 struct double2 {
   double x, y;
 };
@@ -137,17 +168,17 @@ void emu_entry(unsigned lo, unsigned hi) {
   (*t->f)();
   t->done[emu_cur] = true;
 }
+// Workgroups b0, b0 + step, ... < blocks on the calling host thread.
 template <class F>
-void emu_launch(int blocks, int threads, F f) {
-  gridDim.x = blocks;
-  blockDim.x = threads;
+void emu_run_blocks(int b0, int step, int blocks, int threads, F& f, size_t dyn_lds_bytes) {
   constexpr size_t kStack = 512 * 1024;
   std::vector<std::vector<char>> stacks(threads, std::vector<char>(kStack));
   std::vector<char> done_store(threads);
   bool* done = (bool*)done_store.data();
   emu_task<F> task{&f, done};
   const uintptr_t p = (uintptr_t)&task;
-  for (int b = 0; b < blocks; ++b) {
+  emu_dyn_lds.assign(dyn_lds_bytes / 8 + 1, 0.0);
+  for (int b = b0; b < blocks; b += step) {
     blockIdx.x = b;
     emu_lane_ctx.assign(threads, ucontext_t{});
     for (int t = 0; t < threads; ++t) {
@@ -169,4 +200,23 @@ void emu_launch(int blocks, int threads, F f) {
       }
     }
   }
+}
+
+template <class F>
+void emu_launch(int blocks, int threads, F f, size_t dyn_lds_bytes = 0) {
+  gridDim.x = blocks;
+  blockDim.x = threads;
+  emu_run_blocks(0, 1, blocks, threads, f, dyn_lds_bytes);
+}
+
+// All workgroups resident at once, as a cooperative launch: one host thread
+// per workgroup.
+template <class F>
+void emu_launch_grid(int blocks, int threads, F f, size_t dyn_lds_bytes = 0) {
+  gridDim.x = blocks;
+  blockDim.x = threads;
+  std::vector<std::thread> th;
+  for (int b = 0; b < blocks; ++b)
+    th.emplace_back([&, b]() { emu_run_blocks(b, blocks, blocks, threads, f, dyn_lds_bytes); });
+  for (auto& t : th) t.join();
 }
