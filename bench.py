@@ -278,6 +278,71 @@ def single_layout_leg():
     return out
 
 
+NL_BYTES_PER_CELL_SOLVE = 32  # per line solve: iterate, current layer and explicit part read, new iterate written
+
+
+def nonlinear_leg(t_end, cpu_steps, cpu=True):
+    """The paper's method proper on its case-study grid (Sec. 5: 1210 x 100
+    per-layer cells, T0 = 4.2 held on the top face, erf-smoothed pulse of
+    t_per = 0.1, t_src = 0.01, t_trs = 1e-4, xi = 4, zeta = 2), with the
+    synthetic temperature laws of workloads.case_study_laws: the simple
+    iteration of each half step (eps = 1e-7, at most 10 solves, halving
+    beyond) and the step rule of Sec. 4 (t_trs/1000 in transitions, t_src/100
+    elsewhere), from T0 up to t_end in one adi_nl_run call (persistent
+    cooperative kernel).  Throughput counts active cells times accepted
+    steps; the kernel's algorithmic bytes are 32 B per active cell and line
+    solve (solves of both half steps)."""
+    import numpy as np
+    import torch
+
+    from paper_1912_03744_amd import native
+    from paper_1912_03744_amd import workloads as W
+    s = W.case_study()
+    laws = W.case_study_laws()
+    p = native.Problem.from_spec(s)
+    p.set_laws(*laws)
+    p.set_pulse("erf", *W.CASE_STUDY_PULSE)
+    p.set_iteration(1e-7, 10, 1e-14)
+    active = int(np.count_nonzero(p.region_map() != 255))
+    p.set_field(None, W.CASE_STUDY_T0)
+    p.nl_run(2e-6)            # warm-up: kernel set-up, occupancy, first launch
+    p.set_field(None, W.CASE_STUDY_T0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = p.nl_run(t_end)
+    wall = time.perf_counter() - t0
+    T = p.read_field()
+    solves = rep["solves_r"] + rep["solves_z"]
+    achieved = NL_BYTES_PER_CELL_SOLVE * active * solves / wall / 1e9
+    out = {"workload": "case-study cell of Sec. 5, 1210x100 per-layer grid, synthetic laws, erf pulse "
+                       "(t_per 0.1, t_src 0.01, t_trs 1e-4), simple iteration eps 1e-7, step rule of Sec. 4, "
+                       "t = 0 to %g" % t_end,
+           "value": active * rep["steps"] / wall, "unit": "cell-updates/s", "seconds": wall,
+           "steps": rep["steps"], "rejected": rep["rejected"], "solves_r": rep["solves_r"],
+           "solves_z": rep["solves_z"], "us_per_step": wall * 1e6 / max(1, rep["steps"]),
+           "us_per_solve": wall * 1e6 / max(1, solves), "active_cells": active,
+           "t_max": float(np.nanmax(T)), "min_margin": rep["min_margin"],
+           "roofline": {"bound": "hbm", "kernel": "nl_run", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "note": "whole persistent launch (line solves, grid-wide waits, step control) over "
+                                "its wall time"}}
+    p.close()
+    if cpu:
+        import oracle
+        P = oracle.NonlinearProblem(s.geom, s.nr, s.nz, s.h, s.t_inf, s.k, s.rhoc, s.q, s.r_faces, s.z_faces)
+        P.set_laws(*laws)
+        t0 = time.perf_counter()
+        r = P.nl_run(P.initial(W.CASE_STUDY_T0), 0.0, 1.0, kind="erf", pulse_args=W.CASE_STUDY_PULSE, eps=1e-7,
+                     iter_max=10, tau_min=1e-14, max_steps=cpu_steps)
+        sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": active * r["steps"] / sec, "unit": "cell-updates/s", "cores": 1,
+                               "kind": "oracle", "seconds": round(sec, 3),
+                               "sample": "the first %d steps of the same run (inside the first switch-on "
+                                         "transition, %d + %d line solves), single-threaded C -O2"
+                                         % (r["steps"], r["solves_r"], r["solves_z"])}
+    return out
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--counter-workload":
         counter_workload(0)
@@ -301,6 +366,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-only", metavar="R,NW,BPC", default=None,
                     help="run only the batch, in this launch shape (no autotuning), and print its figures")
+    ap.add_argument("--no-nonlinear", action="store_true")
+    ap.add_argument("--nonlinear-t", type=float, default=0.1)
+    ap.add_argument("--cpu-nonlinear-steps", type=int, default=400)
+    ap.add_argument("--nonlinear-only", action="store_true",
+                    help="run only the nonlinear case-study leg and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -314,6 +384,10 @@ def main():
     from paper_1912_03744_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.nonlinear_only:
+        print(json.dumps(nonlinear_leg(args.nonlinear_t, args.cpu_nonlinear_steps, cpu=not args.no_cpu)),
+              flush=True)
+        return
     if args.batch_only:
         shape = tuple(int(x) for x in args.batch_only.split(","))
         print(json.dumps(batch_leg(args.batch_n, args.batch_steps, tune=False, shape=shape)), flush=True)
@@ -388,6 +462,11 @@ def main():
         out["batch"] = batch_leg(args.batch_n, args.batch_steps, tune=not args.no_tune)
         print("bench: batch %.3f s, %.3e cell-updates/s" % (out["batch"]["seconds"], out["batch"]["value"]),
               file=sys.stderr, flush=True)
+    if not args.no_nonlinear:
+        out["nonlinear"] = nonlinear_leg(args.nonlinear_t, args.cpu_nonlinear_steps, cpu=not args.no_cpu)
+        print("bench: nonlinear %.3f s, %d steps, %.3e cell-updates/s" % (
+            out["nonlinear"]["seconds"], out["nonlinear"]["steps"], out["nonlinear"]["value"]),
+            file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps, args.cpu_threaded_steps)
         if "batch" in out:

@@ -31,7 +31,7 @@ struct State {
   int iter_max = 10;
   int grid = 0;
   size_t lds = 0;
-  int Mr = 0, Gr = 0, Mz = 0, Gz = 0;
+  int Mr = 0, Gr = 0, Mz = 0, Gz = 0, wz = 1;
 };
 
 void destroy_state(void* v) {
@@ -43,8 +43,10 @@ void destroy_state(void* v) {
   delete s;
 }
 
-void chunking(int n, int& M, int& G) {
-  M = std::max(MIN_M, (n + 63) / 64);
+// Chunks of a line of n cells over `lanes` lanes: M cells each (at least 3),
+// G chunks.
+void chunking(int n, int lanes, int& M, int& G) {
+  M = std::max(MIN_M, (n + lanes - 1) / lanes);
   G = (n + M - 1) / M;
 }
 
@@ -53,34 +55,43 @@ adi_status get_state(adi_problem p, ProblemCore& core, State** out) {
   State* s = (State*)problem_ext(p);
   if (!s) {
     const int nr = core.P.nr, nz = core.P.nz;
-    int Mr, Gr, Mz, Gz;
-    chunking(nr, Mr, Gr);
-    chunking(nz, Mz, Gz);
+    // r lines: a workgroup of NW waves each; z lines: one wave each, or a
+    // workgroup when the line is long
+    int Mr, Gr, Mz, Gz, wz = 1;
+    chunking(nr, 64 * NW, Mr, Gr);
+    chunking(nz, 64, Mz, Gz);
+    if (Mz > 16) {
+      wz = NW;
+      chunking(nz, 64 * NW, Mz, Gz);
+    }
     if (Mr > MAX_M || Mz > MAX_M)
       return fail(ADI_EUNSUPPORTED, "the nonlinear path takes lines of at most %d cells (grid %d x %d)", 64 * MAX_M, nr,
                   nz);
+    if ((long)nr * nz >= (1L << 28))
+      return fail(ADI_EUNSUPPORTED, "the nonlinear path takes fields of fewer than 2^28 cells (32-bit byte offsets)");
     s = new (std::nothrow) State();
     if (!s) return fail(ADI_ENOMEM, "host allocation failed");
     s->device = core.device;
     s->n = (long)nr * nz;
-    s->Mr = Mr; s->Gr = Gr; s->Mz = Mz; s->Gz = Gz;
+    s->Mr = Mr; s->Gr = Gr; s->Mz = Mz; s->Gz = Gz; s->wz = wz;
     adi_status st = dev_alloc((void**)&s->buf, sizeof(double) * 5 * s->n, core.stream);
     if (st == ADI_OK) st = dev_alloc((void**)&s->ctl, sizeof(Ctl), core.stream);
     if (st != ADI_OK) {
       destroy_state(s);
       return st;
     }
-    const int M = std::max(Mr, Mz);
-    s->lds = sizeof(double) * (4 * 64 * (size_t)M + 2);
+    s->lds = sizeof(double) * nl_lds_doubles(Mr, Mz, wz);
     hipError_t e = hipFuncSetAttribute((const void*)k_nl_run, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s->lds);
     int per_cu = 0, cus = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_nl_run, 64, s->lds);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_nl_run, 64 * NW, s->lds);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, core.device);
     if (e != hipSuccess || per_cu < 1) {
       destroy_state(s);
       return fail(ADI_EDEVICE, "occupancy of the nonlinear kernel: %s (%d per CU)", hipGetErrorString(e), per_cu);
     }
-    s->grid = std::min(per_cu * cus, std::max(nr, nz));
+    // every workgroup resident (cooperative launch); no more workgroups than
+    // the lines need
+    s->grid = std::min(per_cu * cus, std::max(nz, wz == 1 ? (nr + NW - 1) / NW : nr));
     problem_set_ext(p, s, destroy_state);
   }
   *out = s;
@@ -105,13 +116,13 @@ Args make_args(const ProblemCore& core, const State* s) {
   a.div_src = s->div_src;
   a.guard = 1e-9 * s->pulse.ttrs / s->div_trs;
   a.iter_max = s->iter_max;
-  a.Mr = s->Mr; a.Gr = s->Gr; a.Mz = s->Mz; a.Gz = s->Gz;
+  a.Mr = s->Mr; a.Gr = s->Gr; a.Mz = s->Mz; a.Gz = s->Gz; a.wz = s->wz;
   return a;
 }
 
 adi_status launch_run(const ProblemCore& core, const State* s, Args& a) {
   void* args[] = {&a};
-  ADI_HIP(hipLaunchCooperativeKernel((const void*)k_nl_run, dim3(s->grid), dim3(64), args, (unsigned)s->lds,
+  ADI_HIP(hipLaunchCooperativeKernel((const void*)k_nl_run, dim3(s->grid), dim3(64 * NW), args, (unsigned)s->lds,
                                      core.stream));
   return ADI_OK;
 }

@@ -49,6 +49,8 @@ constexpr int ITER_CAP = 64;   // largest iteration limit per half step
 constexpr int MAX_M = 48;      // cells per lane: lines of up to 64 * 48 = 3072 cells
 constexpr int MIN_M = 3;       // a chunk has a first, an interior and a last cell
 constexpr long long SPIN_LIMIT = 1LL << 25;  // bounded grid-wide waits (about a second)
+constexpr unsigned BAR_GROUPS = 8;           // first level of the grid barrier
+constexpr int NW = 4;                        // waves per workgroup
 
 // Temperature laws per region (0 cooler .. 4 terminal): cubic polynomials
 // c0 + c1 T + c2 T^2 + c3 T^3 of the conductivity lambda, the volumetric heat
@@ -87,6 +89,10 @@ struct Ctl {
   unsigned bar_count, bar_gen;
   int abort;
   int pad;
+  struct {
+    unsigned count, gen;
+    unsigned pad[30];   // one 128-byte line per group
+  } bar_sub[8];
   // [attempt parity][half][iteration]: bits of the largest change
   unsigned long long chg[2][2][ITER_CAP];
   unsigned long long pchg;     // periodic-check change
@@ -107,8 +113,36 @@ struct Args {
   int iter_max;
   int single;       // one attempt at the given tau, no step rule
   int attempts;     // attempts in this launch
-  int Mr, Gr, Mz, Gz;
+  int Mr, Gr, Mz, Gz;   // chunking: r lines over NW waves, z lines over wz waves
+  int wz;               // waves per z line: 1 or NW
 };
+
+// Device-scope accesses: coherent across XCDs without fences (see the
+// coherence notes before grid_sync).  Field data goes through buffer loads and
+// stores with the device-scope coherence bit (sc1), which the compiler
+// schedules like ordinary memory operations; the step state and the
+// barrier words through device-scope relaxed atomics.
+constexpr int DEVICE_SCOPE = 0x10;     // cache policy: sc1
+constexpr int RSRC_WORD3 = 0x00020000; // raw buffer, 32-bit data format (gfx9)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* p) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, 0x7fffffff, RSRC_WORD3);
+}
+__device__ __forceinline__ double ldc(__amdgpu_buffer_rsrc_t r, long i) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * 8), 0, DEVICE_SCOPE));
+}
+__device__ __forceinline__ void stc(__amdgpu_buffer_rsrc_t r, long i, double v) {
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)(i * 8), 0, DEVICE_SCOPE);
+}
+template <class T>
+__device__ __forceinline__ T ald(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void ast(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ------------------------------------------------------------- physics --
 
@@ -214,53 +248,80 @@ __device__ double explicit_part(const Args& a, const Laws& L, int i, int j, cons
   const int m = region_at(a.g, i, j);
   if (m == MASKED) return 0.0;
   const long c = (long)j * nr + i;
-  const double Fc = F[c];
+  const __amdgpu_buffer_rsrc_t Fr = rsrc(F);
+  const double Fc = ldc(Fr, c);
   if constexpr (dir == 0) {
-    const double Fm = j > 0 ? F[c - nr] : 0.0, Fp = j < nz - 1 ? F[c + nr] : 0.0;
+    const double Fm = j > 0 ? ldc(Fr, c - nr) : 0.0, Fp = j < nz - 1 ? ldc(Fr, c + nr) : 0.0;
     const Op o = op_z(a, L, i, j, m, Fm, Fc, Fp);
     return o.cc * Fc + o.b + o.lo * Fm + o.up * Fp;
   } else {
-    const double Fm = i > 0 ? F[c - 1] : 0.0, Fp = i < nr - 1 ? F[c + 1] : 0.0;
+    const double Fm = i > 0 ? ldc(Fr, c - 1) : 0.0, Fp = i < nr - 1 ? ldc(Fr, c + 1) : 0.0;
     const Op o = op_r(a, L, i, j, m, Fm, Fc, Fp);
     return o.cc * Fc + o.b + o.lo * Fm + o.up * Fp + law(L.src[m], Fc) * pval;
   }
 }
 
-// ---------------------------------------------------------- grid sync --
+// ------------------------------------------------- coherence and sync --
+//
+// Workgroups on different XCDs share the field buffers, and each XCD has its
+// own L2.  A device-scope release fence would write back a whole L2, and
+// every workgroup would issue one per barrier; instead every access to the
+// shared buffers (the field buffers, the explicit part, the periodic
+// reference, the published step state) is a device-scope relaxed atomic
+// load or store, which is coherent across XCDs by itself, and the barrier
+// only has to order each wave's accesses before its arrival: a wave-scope
+// wait for its own outstanding memory operations (the workgroup barrier's
+// release), then a device-scope atomic arrival.
 
-// Grid-wide barrier over every workgroup of the launch (one wave each).
-// Returns false when the run was aborted: this wave or another one waited
-// past the spin limit.  gen: this workgroup's count of passed barriers.
+// Order the lanes of one wave around LDS exchanges.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Grid-wide barrier over every workgroup of the launch, in two levels: the
+// workgroups of each of 8 groups (by index) count on their group's word, the
+// last of a group counts on the top word, and the last group releases every
+// group's generation word, which its workgroups poll.  Returns false when
+// the run was aborted: some wave waited past the spin limit.  gen: this
+// workgroup's count of passed barriers.
 __device__ bool grid_sync(Ctl* c, unsigned nblocks, unsigned& gen) {
-  int ok = 1;
+  __syncthreads();  // every wave's device-scope accesses have completed
+  __shared__ int ok_s;
   if (threadIdx.x == 0) {
-    __threadfence();
+    int ok = 1;
     const unsigned g0 = gen;
-    const unsigned arrived = atomicAdd(&c->bar_count, 1u);
-    if (arrived == nblocks - 1) {
-      atomicExch(&c->bar_count, 0u);
-      __threadfence();
-      atomicAdd(&c->bar_gen, 1u);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-        if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > SPIN_LIMIT) {
-          atomicExch(&c->abort, 1);
-          ok = 0;
-          break;
-        }
+    const unsigned ngroups = nblocks < BAR_GROUPS ? nblocks : BAR_GROUPS;
+    const unsigned grp = blockIdx.x % ngroups;
+    const unsigned members = (nblocks - grp + ngroups - 1) / ngroups;
+    if (atomicAdd(&c->bar_sub[grp].count, 1u) == members - 1) {
+      ast(&c->bar_sub[grp].count, 0u);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (atomicAdd(&c->bar_count, 1u) == ngroups - 1) {
+        ast(&c->bar_count, 0u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        for (unsigned q = 0; q < ngroups; ++q) ast(&c->bar_sub[q].gen, g0 + 1);
+      }
+    }
+    long long spins = 0;
+    while (ald(&c->bar_sub[grp].gen) == g0) {
+      if (ald(&c->abort)) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > SPIN_LIMIT) {
+        ast(&c->abort, 1);
+        ok = 0;
+        break;
       }
     }
     gen = g0 + 1;
-    __threadfence();
+    ok_s = ok;
   }
-  ok = __shfl(ok, 0);
-  return ok != 0;
+  __syncthreads();
+  return ok_s != 0;
 }
 
 __device__ __forceinline__ unsigned long long as_bits(double x) { return (unsigned long long)__double_as_longlong(x); }
@@ -277,44 +338,60 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // -------------------------------------------------------- line solver --
 
-// Solve one line of a half step.  dir 0: row j = line of eq. 12, iterate Ts,
-// current layer Tc = T; dir 1: column i = line of eq. 14, Ts the iterate, Tc =
-// T-bar.  E holds the explicit part (computed here when `first`).  Writes the
-// new iterate to out and returns the line's largest change over active cells
-// (the same value in every lane).
+// Solve one line of a half step with NWL waves (1 or NW): dir 0, row
+// `line`, the line system of eq. 12 (iterate Ts, current layer Tc = T);
+// dir 1, column `line`, that of eq. 14 (Tc = T-bar).  The rows are assembled
+// on the fly from the staged iterate, current layer and explicit part (E,
+// computed here on the first iteration); the line is solved by a partition
+// method: lane k of the line's 64 NWL lanes eliminates chunk k of M
+// consecutive cells by Thomas with two spike columns (responses to the
+// chunk's first and last unknowns), the chunk-end unknowns form a reduced
+// tridiagonal system of one row per lane, solved by parallel cyclic
+// reduction (wavefront shuffles inside a wave, LDS across the waves of the
+// line), then each lane substitutes back.  Writes the new iterate to out and
+// returns the largest |x - Ts| over the line's active cells (the same value
+// in every lane of the line).
 //
-// LDS (per wave): ts[64M + 2] (iterate with a zero cell before and after),
-// tc[64M] (current layer, then the eliminated right-hand side y', then the
-// solution), ev[64M] (explicit part, then the eliminated spike v'), cp[64M]
-// (eliminated super-diagonal c').
-template <int dir>
+// LDS (per line): ts[L + 2] (iterate with a zero cell before and after),
+// tc[L] (current layer, then the eliminated right-hand side y', then the
+// solution), ev[L] (explicit part, then the eliminated spike v'), cp[L]
+// (eliminated super-diagonal c'), L = 64 NWL M, plus for NWL > 1 an
+// exchange space of 4 x 64 NWL doubles.
+template <int dir, int NWL>
 __device__ double solve_line(const Args& a, const Laws& laws, int line, const double* Ts, const double* Tc, double* E,
                              double* out, bool first, double ta, double pval, double* lds) {
   const int nr = a.P.nr;
   const int n = dir == 0 ? a.P.nr : a.P.nz;
   const int M = dir == 0 ? a.Mr : a.Mz;
   const int G = dir == 0 ? a.Gr : a.Gz;
-  const int L = 64 * M;
+  constexpr int NL = 64 * NWL;                          // lanes of the line
+  const int L = NL * M;
   double* ts = lds;
   double* tc = ts + L + 2;
   double* ev = tc + L;
   double* cp = ev + L;
-  const int lane = threadIdx.x;
+  double* xch = cp + L;                                 // NWL > 1: 4 x NL exchange
+  const int lane = NWL == 1 ? (threadIdx.x & 63) : (int)threadIdx.x;
+  auto sync = [&]() {
+    if constexpr (NWL == 1) wave_sync();
+    else __syncthreads();
+  };
   auto addr = [&](int e) -> long { return dir == 0 ? (long)line * nr + e : (long)e * nr + line; };
+  const __amdgpu_buffer_rsrc_t Tsr = rsrc(Ts), Tcr = rsrc(Tc), Er = rsrc(E), Or = rsrc(out);
   // stage the line (lane-contiguous: coalesced along rows)
-#pragma unroll 1
-  for (int e = lane; e < L; e += 64) {
+#pragma unroll 4
+  for (int e = lane; e < L; e += NL) {
     double vs = 0.0, vc = 0.0, ve = 0.0;
     if (e < n) {
       const long c = addr(e);
-      vs = Ts[c];
-      vc = Tc[c];
+      vs = ldc(Tsr, c);
+      vc = ldc(Tcr, c);
       if (first) {
         if constexpr (dir == 0) ve = explicit_part<0>(a, laws, e, line, Tc, pval);
         else ve = explicit_part<1>(a, laws, line, e, Tc, pval);
-        E[c] = ve;
+        stc(Er, c, ve);
       } else {
-        ve = E[c];
+        ve = ldc(Er, c);
       }
     }
     ts[e + 1] = vs;
@@ -325,7 +402,7 @@ __device__ double solve_line(const Args& a, const Laws& laws, int line, const do
     ts[0] = 0.0;
     ts[L + 1] = 0.0;
   }
-  __syncthreads();
+  sync();
 
   // row p of the line: a x[p-1] + b x[p] + c x[p+1] = d; identity for cells
   // outside the domain and past the line's end
@@ -349,12 +426,13 @@ __device__ double solve_line(const Args& a, const Laws& laws, int line, const do
     rd += o.b;
   };
 
-  // chunk of this lane: cells k*M .. k*M + M - 1.  One pass over the chunk:
+  // chunk of this lane: cells k M .. k M + M - 1.  One pass over the chunk:
   // the first and last rows are kept, the interior rows 1 .. M-2 are
   // eliminated by Thomas with the first unknown's column (v') on the right;
   // the last interior row's super-diagonal goes to the last unknown's column
   // (w')
   const int p0 = lane * M;
+  const int pl = p0 + M - 1;
   double a0 = 0.0, b0 = 1.0, c0 = 0.0, d0 = 0.0;   // first row
   double aL = 0.0, bL = 1.0, cL = 0.0, dL = 0.0;   // last row
   double cprev = 0.0, yprev = 0.0, vprev = 0.0, wlast = 0.0;
@@ -385,73 +463,154 @@ __device__ double solve_line(const Args& a, const Laws& laws, int line, const do
     }
   }
   // responses of the first interior cell to the chunk's data (y1), first
-  // unknown (v1) and last unknown (w1), by back substitution of the spikes
-  double y1 = tc[p0 + M - 2], v1 = ev[p0 + M - 2], w1 = wlast;
+  // unknown (v1) and last unknown (w1)
+  const int pi = p0 + M - 2;
+  double y1 = tc[pi], v1 = ev[pi], w1 = wlast;
 #pragma unroll 1
   for (int t = M - 3; t >= 1; --t) {
     const int p = p0 + t;
-    const double c = cp[p];
-    y1 = tc[p] - c * y1;
-    v1 = ev[p] - c * v1;
-    w1 = -c * w1;
+    const double cq = cp[p];
+    y1 = tc[p] - cq * y1;
+    v1 = ev[p] - cq * v1;
+    w1 = -cq * w1;
   }
-  const double yl = tc[p0 + M - 2], vl = ev[p0 + M - 2], wl = wlast;
+  const double yl = tc[pi], vl = ev[pi], wl = wlast;
   // reduced rows: first cell s, last cell e of chunk k
   //   a0 x_e(k-1) + (b0 + c0 v1) x_s + c0 w1 x_e = d0 - c0 y1
   //   aL vl x_s + (bL + aL wl) x_e + cL x_s(k+1) = dL - aL yl
   const double BS = b0 + c0 * v1;
   const double qA = a0 / BS, qC = c0 * w1 / BS, qR = (d0 - c0 * y1) / BS;
   const double AE = aL * vl, BE = bL + aL * wl, RE = dL - aL * yl;
+  // the next chunk's first-row terms (lane k + 1)
+  double nA, nC, nR;
+  {
+    const double sA = __shfl_down(qA, 1), sC = __shfl_down(qC, 1), sR = __shfl_down(qR, 1);
+    nA = sA;
+    nC = sC;
+    nR = sR;
+    if constexpr (NWL > 1) {
+      xch[lane] = qA;
+      xch[NL + lane] = qC;
+      xch[2 * NL + lane] = qR;
+      __syncthreads();
+      if ((lane & 63) == 63 && lane + 1 < NL) {
+        nA = xch[lane + 1];
+        nC = xch[NL + lane + 1];
+        nR = xch[2 * NL + lane + 1];
+      }
+      __syncthreads();
+    }
+  }
   // eliminate every x_s: one row per lane in the chunk-end unknowns x_e
-  const double nA = __shfl_down(qA, 1), nC = __shfl_down(qC, 1), nR = __shfl_down(qR, 1);
   double al = -AE * qA;
   double be = BE - AE * qC - cL * nA;
   double ga = -cL * nC;
   double de = RE - AE * qR - cL * nR;
-  // parallel cyclic reduction over the lanes
+  // parallel cyclic reduction: strides below 64 by shuffles inside the wave
+  // (every lane takes part in every shuffle), larger strides through LDS
 #pragma unroll 1
-  for (int s = 1; s < G; s <<= 1) {
-    const bool hasm = lane >= s, hasp = lane + s < 64;
+  for (int s = 1; s < G && s < 64; s <<= 1) {
+    const int wl_ = lane & 63;
+    const bool hasm = lane >= s, hasp = lane + s < G;
     const double am = __shfl_up(al, s), bm = __shfl_up(be, s), gm = __shfl_up(ga, s), dm = __shfl_up(de, s);
     const double ap = __shfl_down(al, s), bp = __shfl_down(be, s), gp = __shfl_down(ga, s), dp = __shfl_down(de, s);
-    const double k1 = hasm ? al / bm : 0.0;
-    const double k2 = hasp ? ga / bp : 0.0;
-    const double nal = hasm ? -am * k1 : 0.0;
-    const double nga = hasp ? -gp * k2 : 0.0;
-    const double nbe = be - (hasm ? gm * k1 : 0.0) - (hasp ? ap * k2 : 0.0);
-    const double nde = de - (hasm ? dm * k1 : 0.0) - (hasp ? dp * k2 : 0.0);
+    // across the wave boundary (NWL > 1) the partner sits in another wave:
+    // its values come from LDS below
+    double Am = am, Bm = bm, Gm = gm, Dm = dm, Ap = ap, Bp = bp, Gp = gp, Dp = dp;
+    if constexpr (NWL > 1) {
+      xch[lane] = al;
+      xch[NL + lane] = be;
+      xch[2 * NL + lane] = ga;
+      xch[3 * NL + lane] = de;
+      __syncthreads();
+      if (hasm && wl_ < s) {
+        Am = xch[lane - s]; Bm = xch[NL + lane - s]; Gm = xch[2 * NL + lane - s]; Dm = xch[3 * NL + lane - s];
+      }
+      if (hasp && wl_ + s >= 64) {
+        Ap = xch[lane + s]; Bp = xch[NL + lane + s]; Gp = xch[2 * NL + lane + s]; Dp = xch[3 * NL + lane + s];
+      }
+      __syncthreads();
+    }
+    const double k1 = hasm ? al / Bm : 0.0;
+    const double k2 = hasp ? ga / Bp : 0.0;
+    const double nal = hasm ? -Am * k1 : 0.0;
+    const double nga = hasp ? -Gp * k2 : 0.0;
+    const double nbe = be - (hasm ? Gm * k1 : 0.0) - (hasp ? Ap * k2 : 0.0);
+    const double nde = de - (hasm ? Dm * k1 : 0.0) - (hasp ? Dp * k2 : 0.0);
     al = nal;
     be = nbe;
     ga = nga;
     de = nde;
   }
-  const double xe = de / be;
-  const double xup = __shfl_up(xe, 1);  // every lane takes part in the shuffle
-  const double xe_prev = lane > 0 ? xup : 0.0;
+  if constexpr (NWL > 1) {
+#pragma unroll 1
+    for (int s = 64; s < G; s <<= 1) {
+      const bool hasm = lane >= s, hasp = lane + s < G;
+      xch[lane] = al;
+      xch[NL + lane] = be;
+      xch[2 * NL + lane] = ga;
+      xch[3 * NL + lane] = de;
+      __syncthreads();
+      const double Am = hasm ? xch[lane - s] : 0.0, Bm = hasm ? xch[NL + lane - s] : 1.0;
+      const double Gm = hasm ? xch[2 * NL + lane - s] : 0.0, Dm = hasm ? xch[3 * NL + lane - s] : 0.0;
+      const double Ap = hasp ? xch[lane + s] : 0.0, Bp = hasp ? xch[NL + lane + s] : 1.0;
+      const double Gp = hasp ? xch[2 * NL + lane + s] : 0.0, Dp = hasp ? xch[3 * NL + lane + s] : 0.0;
+      __syncthreads();
+      const double k1 = hasm ? al / Bm : 0.0;
+      const double k2 = hasp ? ga / Bp : 0.0;
+      const double nal = hasm ? -Am * k1 : 0.0;
+      const double nga = hasp ? -Gp * k2 : 0.0;
+      const double nbe = be - (hasm ? Gm * k1 : 0.0) - (hasp ? Ap * k2 : 0.0);
+      const double nde = de - (hasm ? Dm * k1 : 0.0) - (hasp ? Dp * k2 : 0.0);
+      al = nal;
+      be = nbe;
+      ga = nga;
+      de = nde;
+    }
+  }
+  const double xe = lane < G ? de / be : 0.0;
+  // the previous chunk's last unknown (lane k - 1)
+  double xe_prev;
+  {
+    const double up = __shfl_up(xe, 1);  // every lane takes part in the shuffle
+    xe_prev = (lane & 63) > 0 ? up : 0.0;
+    if constexpr (NWL > 1) {
+      xch[lane] = xe;
+      __syncthreads();
+      if ((lane & 63) == 0 && lane > 0) xe_prev = xch[lane - 1];
+      __syncthreads();
+    }
+  }
   const double xs = qR - qA * xe_prev - qC * xe;
   // back substitution into the chunk; largest change over active cells
+  // (identity rows outside the domain keep 0, and the iterate is 0 there:
+  // they never change)
   double dmax = 0.0;
-  auto active = [&](int p) {
-    if (p >= n) return false;
-    const int i = dir == 0 ? p : line, j = dir == 0 ? line : p;
-    return region_at(a.g, i, j) != MASKED;
-  };
+  if (pl < n) dmax = fabs(xe - ts[pl + 1]);
+  tc[pl] = xe;
   double x = xe;
-  if (active(p0 + M - 1)) dmax = fabs(xe - ts[p0 + M]);
-  tc[p0 + M - 1] = xe;
 #pragma unroll 1
   for (int t = M - 2; t >= 1; --t) {
     const int p = p0 + t;
     x = t == M - 2 ? tc[p] + ev[p] * xs + wl * xe : tc[p] + ev[p] * xs - cp[p] * x;
-    if (active(p)) dmax = nan_max(dmax, fabs(x - ts[p + 1]));
+    if (p < n) dmax = nan_max(dmax, fabs(x - ts[p + 1]));
     tc[p] = x;
   }
-  if (active(p0)) dmax = nan_max(dmax, fabs(xs - ts[p0 + 1]));
+  if (p0 < n) dmax = nan_max(dmax, fabs(xs - ts[p0 + 1]));
   tc[p0] = xs;
-  __syncthreads();
-  for (int e = lane; e < n; e += 64) out[addr(e)] = tc[e];
-  __syncthreads();
-  return wave_max(dmax);
+  sync();
+#pragma unroll 4
+  for (int e = lane; e < n; e += NL) stc(Or, addr(e), tc[e]);
+  dmax = wave_max(dmax);
+  if constexpr (NWL > 1) {
+    if ((lane & 63) == 0) xch[lane >> 6] = dmax;
+    __syncthreads();
+    for (int q = 0; q < NWL; ++q) dmax = nan_max(dmax, xch[q]);
+    __syncthreads();
+  } else {
+    sync();
+  }
+  return dmax;
 }
 
 // ------------------------------------------------------- step control --
@@ -477,35 +636,36 @@ __device__ double next_switch(const Pulse& p, double t, double guard) {
   return best;
 }
 
-// Size of the next step from time c->t (the rule of Sec. 4: t_trs/div_trs in
-// a transition, t_src/div_src elsewhere, never across a switch point or
-// transition end, never past t_end), or the end of the run.
-__device__ void begin_step(const Args& a, Ctl* c) {
-  if (c->steps >= c->max_steps) {
-    c->status = END_STEPS;
+// Size of the next step from time t (the rule of Sec. 4: t_trs/div_trs in a
+// transition, t_src/div_src elsewhere, never across a switch point or
+// transition end, never past t_end), or the end of the run (status).
+__device__ void begin_step(const Args& a, double t, long long steps, long long max_steps, double t_end,
+                           double& tau_out, int& ends_out, int& status) {
+  if (steps >= max_steps) {
+    status = END_STEPS;
     return;
   }
-  if (!(c->t_end - c->t > a.guard)) {
-    c->status = END_TIME;
+  if (!(t_end - t > a.guard)) {
+    status = END_TIME;
     return;
   }
   const Pulse& p = a.pulse;
-  double tau = (p.kind != 0 && in_transition(p, c->t + a.guard)) ? p.ttrs / a.div_trs : p.tsrc / a.div_src;
+  double tau = (p.kind != 0 && in_transition(p, t + a.guard)) ? p.ttrs / a.div_trs : p.tsrc / a.div_src;
   int ends = 0;
   if (p.kind != 0) {
-    const double b = next_switch(p, c->t, a.guard);
-    if (b - c->t <= tau) {
-      tau = b - c->t;
+    const double b = next_switch(p, t, a.guard);
+    if (b - t <= tau) {
+      tau = b - t;
       const double k = floor(b / p.tper + 0.5);
       ends = fabs(b - k * p.tper) <= a.guard;
     }
   }
-  if (c->t_end - c->t < tau) {
-    tau = c->t_end - c->t;
+  if (t_end - t < tau) {
+    tau = t_end - t;
     ends = 0;
   }
-  c->tau = tau;
-  c->ends_period = ends;
+  tau_out = tau;
+  ends_out = ends;
 }
 
 __device__ void note_margin(Ctl* c, double chg, double bound) {
@@ -515,6 +675,19 @@ __device__ void note_margin(Ctl* c, double chg, double bound) {
 
 // ------------------------------------------------------------- kernel --
 
+// Dynamic LDS of a workgroup (doubles): an r line over the whole workgroup
+// (4 staged arrays of 64 NW Mr cells, 2 halo cells, 4 x 64 NW exchange), z
+// lines one wave each (NW slices of 4 x 64 Mz + 2) or over the whole
+// workgroup.
+__host__ __device__ inline size_t nl_lds_doubles(int Mr, int Mz, int wz) {
+  const size_t r = 4 * (size_t)(64 * NW) * Mr + 2 + 4 * (size_t)(64 * NW);
+  const size_t z = wz == 1 ? (size_t)NW * (4 * 64 * (size_t)Mz + 2)
+                           : 4 * (size_t)(64 * NW) * Mz + 2 + 4 * (size_t)(64 * NW);
+  return r > z ? r : z;
+}
+
+// The two buffer indices (of 0..3) other than x and y (the two lowest other
+// than x when x == y).
 __device__ __forceinline__ void other_two(int x, int y, int& u, int& v) {
   u = -1;
   v = -1;
@@ -525,22 +698,42 @@ __device__ __forceinline__ void other_two(int x, int y, int& u, int& v) {
     }
 }
 
-__global__ void __launch_bounds__(64) k_nl_run(Args a) {
-  HIP_DYNAMIC_SHARED(double, lds)
+// Step state every workgroup reads at the start of an attempt, published by
+// workgroup 0 with device-scope stores.
+__device__ __forceinline__ void publish(Ctl* c, double t, double tau, int cur, long long steps, long long rej,
+                                        int ends, int status) {
+  ast(&c->t, t);
+  ast(&c->tau, tau);
+  ast(&c->cur, cur);
+  ast(&c->steps, steps);
+  ast(&c->rejected, rej);
+  ast(&c->ends_period, ends);
+  ast(&c->status, status);
+}
+
+__global__ void __launch_bounds__(64 * NW) k_nl_run(Args a) {
+  HIP_DYNAMIC_SHARED(double, lds_all)
   __shared__ Laws laws;
-  for (int q = threadIdx.x; q < 60; q += 64) (&laws.lam[0][0])[q] = (&a.L.lam[0][0])[q];
+  for (int q = threadIdx.x; q < 60; q += blockDim.x) (&laws.lam[0][0])[q] = (&a.L.lam[0][0])[q];
   __syncthreads();
   Ctl* c = a.ctl;
   const unsigned nb = gridDim.x;
-  const int w = blockIdx.x;
+  const int wv = threadIdx.x >> 6;
+  const int w = blockIdx.x * NW + wv;             // this wave
+  const int nw = (int)nb * NW;                    // waves in the grid
+  // LDS: an r line uses the workgroup's whole space; z lines one slice per
+  // wave when a wave takes a line alone
+  double* lds_z = a.wz == 1 ? lds_all + (size_t)wv * (4 * 64 * a.Mz + 2) : lds_all;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   unsigned gen = 0;
-  if (threadIdx.x == 0) gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) gen = ald(&c->bar_sub[0].gen);
   for (int att = 0; att < a.attempts; ++att) {
-    if (__hip_atomic_load(&c->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != RUNNING) break;
-    const long long par = (c->steps + c->rejected) & 1;
-    const double t = c->t, tau = c->tau, ta = 0.5 * tau;
-    const int cur = c->cur;
-    const bool ends_period = c->ends_period != 0;  // this step lands on a period start
+    if (ald(&c->status) != RUNNING) break;
+    const long long steps0 = ald(&c->steps), rej0 = ald(&c->rejected);
+    const long long par = (steps0 + rej0) & 1;
+    const double t = ald(&c->t), tau = ald(&c->tau), ta = 0.5 * tau;
+    const int cur = ald(&c->cur);
+    const bool ends_period = ald(&c->ends_period) != 0;  // this step lands on a period start
     const double pval = pulse_at(a.pulse, t + 0.5 * tau);
     // half step 1 (eq. 12): lines along r, iterate from T
     int in = cur, A0, A1, bar = -1, it_r = -1, it_z = 0;
@@ -549,11 +742,11 @@ __global__ void __launch_bounds__(64) k_nl_run(Args a) {
     for (int s = 0; s < a.iter_max; ++s) {
       const int o = (s & 1) ? A1 : A0;
       double lmax = 0.0;
-      for (int j = w; j < a.P.nz; j += nb)
-        lmax = nan_max(lmax, solve_line<0>(a, laws, j, a.F[in], a.F[cur], a.E, a.F[o], s == 0, ta, pval, lds));
+      for (int j = blockIdx.x; j < a.P.nz; j += nb)
+        lmax = nan_max(lmax, solve_line<0, NW>(a, laws, j, a.F[in], a.F[cur], a.E, a.F[o], s == 0, ta, pval, lds_all));
       if (threadIdx.x == 0 && !(lmax <= 0.0)) atomicMax(&c->chg[par][0][s], as_bits(lmax));
       if (!grid_sync(c, nb, gen)) return;
-      chg_r = from_bits(__hip_atomic_load(&c->chg[par][0][s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      chg_r = from_bits(ald(&c->chg[par][0][s]));
       in = o;
       if (chg_r < a.eps) {
         bar = o;
@@ -571,11 +764,18 @@ __global__ void __launch_bounds__(64) k_nl_run(Args a) {
       for (int s = 0; s < a.iter_max; ++s) {
         const int o = (s & 1) ? B1 : B0;
         double lmax = 0.0;
-        for (int i = w; i < a.P.nr; i += nb)
-          lmax = nan_max(lmax, solve_line<1>(a, laws, i, a.F[in], a.F[bar], a.E, a.F[o], s == 0, ta, pval, lds));
-        if (threadIdx.x == 0 && !(lmax <= 0.0)) atomicMax(&c->chg[par][1][s], as_bits(lmax));
+        if (a.wz == 1) {
+          for (int i = w; i < a.P.nr; i += nw)
+            lmax = nan_max(lmax, solve_line<1, 1>(a, laws, i, a.F[in], a.F[bar], a.E, a.F[o], s == 0, ta, pval, lds_z));
+          if ((threadIdx.x & 63) == 0 && !(lmax <= 0.0)) atomicMax(&c->chg[par][1][s], as_bits(lmax));
+        } else {
+          for (int i = blockIdx.x; i < a.P.nr; i += nb)
+            lmax = nan_max(lmax, solve_line<1, NW>(a, laws, i, a.F[in], a.F[bar], a.E, a.F[o], s == 0, ta, pval,
+                                                   lds_all));
+          if (threadIdx.x == 0 && !(lmax <= 0.0)) atomicMax(&c->chg[par][1][s], as_bits(lmax));
+        }
         if (!grid_sync(c, nb, gen)) return;
-        chg_z = from_bits(__hip_atomic_load(&c->chg[par][1][s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        chg_z = from_bits(ald(&c->chg[par][1][s]));
         in = o;
         if (chg_z < a.eps) {
           it_z = s + 1;
@@ -584,12 +784,13 @@ __global__ void __launch_bounds__(64) k_nl_run(Args a) {
       }
     }
     const bool ok = bar >= 0 && it_z > 0;
-    // step control (one lane); the next attempt's change words are cleared
-    // here: every wave has read them before the barrier that ended that
-    // attempt's last iteration
-    if (w == 0 && threadIdx.x == 0) {
+    // step control (one lane).  The fields only this lane reads (counters,
+    // margins, the log, the last attempt's record) are plain; the next
+    // attempt's change words are cleared here: every wave read them before
+    // the barrier that ended that attempt's last iteration
+    if (lead) {
       for (int h = 0; h < 2; ++h)
-        for (int s = 0; s < ITER_CAP; ++s) c->chg[par ^ 1][h][s] = 0ull;
+        for (int s = 0; s < ITER_CAP; ++s) ast(&c->chg[par ^ 1][h][s], 0ull);
       c->last_it[0] = it_r;
       c->last_it[1] = it_z;
       c->last_chg[0] = chg_r;
@@ -597,54 +798,61 @@ __global__ void __launch_bounds__(64) k_nl_run(Args a) {
       note_margin(c, chg_r, a.eps);
       if (bar >= 0) note_margin(c, chg_z, a.eps);
       c->accepted = ok;
+      double nt = t, ntau = tau;
+      int ncur = cur, nends = ends_period, status = RUNNING;
+      long long nsteps = steps0, nrej = rej0;
       if (ok) {
-        if (a.log && c->steps < a.log_cap) {
-          double* r = a.log + 4 * c->steps;
-          r[0] = c->t;
+        if (a.log && steps0 < a.log_cap) {
+          double* r = a.log + 4 * steps0;
+          r[0] = t;
           r[1] = tau;
           r[2] = it_r;
           r[3] = it_z;
         }
-        c->t = c->t + tau;
-        c->steps += 1;
+        nt = t + tau;
+        nsteps += 1;
         c->solves_r += it_r;
         c->solves_z += it_z;
-        c->cur = in;
-        c->pchg = 0ull;
+        ncur = in;
+        ast(&c->pchg, 0ull);
       } else {
-        c->rejected += 1;
+        nrej += 1;
       }
       if (a.single) {
-        c->status = END_SINGLE;
+        status = END_SINGLE;
       } else if (!ok) {
-        c->tau = 0.5 * tau;
-        c->ends_period = 0;
-        if (c->tau < a.tau_min) c->status = FAIL_TAU;
+        ntau = 0.5 * tau;
+        nends = 0;
+        if (ntau < a.tau_min) status = FAIL_TAU;
       } else if (!(ends_period && a.ptol > 0.0)) {
-        begin_step(a, c);
+        begin_step(a, nt, nsteps, c->max_steps, c->t_end, ntau, nends, status);
       }
-      __threadfence();
+      publish(c, nt, ntau, ncur, nsteps, nrej, nends, status);
     }
     if (!grid_sync(c, nb, gen)) return;
     // periodic regime: at a period start, compare T with the field of the
     // previous period start
     if (ok && !a.single && ends_period && a.ptol > 0.0) {
       const long n = (long)a.P.nr * a.P.nz;
-      const double* T = a.F[c->cur];
+      const __amdgpu_buffer_rsrc_t Tr = rsrc(a.F[ald(&c->cur)]), Pr = rsrc(a.prev);
       double lmax = 0.0;
-      for (long e = (long)w * 64 + threadIdx.x; e < n; e += (long)nb * 64) {
-        if (region_at(a.g, (int)(e % a.P.nr), (int)(e / a.P.nr)) != MASKED) lmax = nan_max(lmax, fabs(T[e] - a.prev[e]));
-        a.prev[e] = T[e];
+      for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)nb * blockDim.x) {
+        const double v = ldc(Tr, e);
+        if (region_at(a.g, (int)(e % a.P.nr), (int)(e / a.P.nr)) != MASKED) lmax = nan_max(lmax, fabs(v - ldc(Pr, e)));
+        stc(Pr, e, v);
       }
       lmax = wave_max(lmax);
-      if (threadIdx.x == 0 && !(lmax <= 0.0)) atomicMax(&c->pchg, as_bits(lmax));
+      if ((threadIdx.x & 63) == 0 && !(lmax <= 0.0)) atomicMax(&c->pchg, as_bits(lmax));
       if (!grid_sync(c, nb, gen)) return;
-      if (w == 0 && threadIdx.x == 0) {
-        const double d = from_bits(c->pchg);
+      if (lead) {
+        const double d = from_bits(ald(&c->pchg));
         note_margin(c, d, a.ptol);
-        if (d < a.ptol) c->status = END_PERIODIC;
-        else begin_step(a, c);
-        __threadfence();
+        double nt = ald(&c->t), ntau = ald(&c->tau);
+        int nends = 0, status = RUNNING;
+        const long long nsteps = ald(&c->steps);
+        if (d < a.ptol) status = END_PERIODIC;
+        else begin_step(a, nt, nsteps, c->max_steps, c->t_end, ntau, nends, status);
+        publish(c, nt, ntau, ald(&c->cur), nsteps, ald(&c->rejected), nends, status);
       }
       if (!grid_sync(c, nb, gen)) return;
     }
@@ -653,7 +861,13 @@ __global__ void __launch_bounds__(64) k_nl_run(Args a) {
 
 // Set up the first step of a run (one lane).
 __global__ void k_nl_begin(Args a) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) begin_step(a, a.ctl);
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    Ctl* c = a.ctl;
+    double tau = c->tau;
+    int ends = 0, status = RUNNING;
+    begin_step(a, c->t, c->steps, c->max_steps, c->t_end, tau, ends, status);
+    publish(c, c->t, tau, c->cur, c->steps, c->rejected, ends, status);
+  }
 }
 
 __global__ void k_nl_copy(const double* __restrict__ src, double* __restrict__ dst, long n) {

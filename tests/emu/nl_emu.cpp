@@ -16,6 +16,7 @@
 //        t0 t_end_or_tau max_steps log_cap
 //        field (nz*nr)
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "hip/hip_runtime.h"
@@ -77,8 +78,8 @@ int main(int argc, char** argv) {
   const double* zfp = has_faces ? zfi.data() : nullptr;
   emu_launch(1, 64, [&]() { build_geometry(P, rfp, zfp, g, ranges.data()); });
 
-  auto chunk = [](int len, int& M, int& G) {
-    M = std::max(3, (len + 63) / 64);
+  auto chunk = [](int len, int lanes, int& M, int& G) {
+    M = std::max(3, (len + lanes - 1) / lanes);
     G = (len + M - 1) / M;
   };
   Ctl c;
@@ -100,9 +101,14 @@ int main(int argc, char** argv) {
   a.eps = ctl6[0]; a.iter_max = iter_max; a.tau_min = ctl6[1]; a.div_trs = ctl6[2]; a.div_src = ctl6[3];
   a.ptol = ctl6[4];
   a.guard = 1e-9 * pu.ttrs / a.div_trs;
-  chunk(nr, a.Mr, a.Gr);
-  chunk(nz, a.Mz, a.Gz);
-  const size_t lds = sizeof(double) * (4 * 64 * (size_t)std::max(a.Mr, a.Mz) + 2);
+  chunk(nr, 64 * NW, a.Mr, a.Gr);
+  chunk(nz, 64, a.Mz, a.Gz);
+  a.wz = 1;
+  if (a.Mz > 16 || getenv("NL_EMU_WZ_BLOCK")) {
+    a.wz = NW;
+    chunk(nz, 64 * NW, a.Mz, a.Gz);
+  }
+  const size_t lds = sizeof(double) * nl_lds_doubles(a.Mr, a.Mz, a.wz);
   c.t = run4[0];
   c.min_margin = INFINITY;
   c.max_steps = (long long)run4[2];
@@ -121,7 +127,7 @@ int main(int argc, char** argv) {
     emu_launch(1, 64, [&]() { k_nl_begin(a); });
   }
   for (int launches = 0; launches < 100000; ++launches) {
-    emu_launch_grid(grid, 64, [&]() { k_nl_run(a); }, lds);
+    emu_launch_grid(grid, 64 * NW, [&]() { k_nl_run(a); }, lds);
     if (c.status != RUNNING || c.abort) break;
   }
   const double* out = a.F[c.cur];

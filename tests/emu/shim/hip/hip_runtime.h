@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <thread>
 #include <ucontext.h>
 #include <vector>
@@ -44,17 +45,41 @@ inline emu_dim3 gridDim, blockDim;
 inline thread_local ucontext_t emu_main_ctx;
 inline thread_local std::vector<ucontext_t> emu_lane_ctx;
 inline thread_local int emu_cur = 0;
-inline void __syncthreads() { swapcontext(&emu_lane_ctx[emu_cur], &emu_main_ctx); }
-inline void __builtin_amdgcn_wave_barrier() { __syncthreads(); }
+inline void emu_yield() { swapcontext(&emu_lane_ctx[emu_cur], &emu_main_ctx); }
+// Barriers count arrivals: a lane waits (yielding) until every lane of its
+// workgroup (__syncthreads) or of its wave (wave barrier) has arrived.
+inline thread_local unsigned emu_blk_count = 0, emu_blk_gen = 0;
+inline thread_local unsigned emu_wave_count[16], emu_wave_gen[16];
+inline void __syncthreads() {
+  const unsigned g = emu_blk_gen;
+  if (++emu_blk_count == blockDim.x) {
+    emu_blk_count = 0;
+    ++emu_blk_gen;
+  } else {
+    while (emu_blk_gen == g) emu_yield();
+  }
+}
+inline void __builtin_amdgcn_wave_barrier() {
+  const int w = threadIdx.x >> 6;
+  const unsigned width = std::min(64u, blockDim.x - 64u * w);
+  const unsigned g = emu_wave_gen[w];
+  if (++emu_wave_count[w] == width) {
+    emu_wave_count[w] = 0;
+    ++emu_wave_gen[w];
+  } else {
+    while (emu_wave_gen[w] == g) emu_yield();
+  }
+}
 
 // one exchange slot per lane; a value is published, then read from lane src
 inline thread_local long long emu_slot[1024];
+inline void __builtin_amdgcn_wave_barrier();
 inline long long emu_exchange(long long v, int src_lane_in_wave, bool valid, long long fallback) {
   const int l = threadIdx.x;
   emu_slot[l] = v;
-  __syncthreads();
+  __builtin_amdgcn_wave_barrier();
   const long long r = valid ? emu_slot[l - (l & 63) + src_lane_in_wave] : fallback;
-  __syncthreads();
+  __builtin_amdgcn_wave_barrier();
   return r;
 }
 inline long long __double_as_longlong(double d) {
@@ -136,7 +161,16 @@ inline unsigned long long atomicMax(unsigned long long* p, unsigned long long v)
 }
 #define __HIP_MEMORY_SCOPE_AGENT 0
 template <class T>
-inline T __hip_atomic_load(T* p, int, int) { return __atomic_load_n(p, __ATOMIC_SEQ_CST); }
+inline T __hip_atomic_load(const T* p, int, int) {
+  T r;
+  __atomic_load(const_cast<T*>(p), &r, __ATOMIC_SEQ_CST);
+  return r;
+}
+template <class T, class U>
+inline void __hip_atomic_store(T* p, U v, int, int) {
+  T x = (T)v;
+  __atomic_store(p, &x, __ATOMIC_SEQ_CST);
+}
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::yield(); }
 inline int __shfl(int v, int src, int w = 64) { return (int)emu_exchange(v, src & 63, true, v); }
@@ -146,6 +180,22 @@ inline double __shfl(double v, int src, int w = 64) {
 inline double __shfl_xor(double v, int mask, int w = 64) {
   const int lane = threadIdx.x & 63;
   return __longlong_as_double(emu_exchange(__double_as_longlong(v), lane ^ mask, true, __double_as_longlong(v)));
+}
+// raw buffer accesses (device-scope coherent loads and stores of 8 bytes)
+struct __amdgpu_buffer_rsrc_t {
+  char* base;
+};
+inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void* p, short, int, int) { return {(char*)p}; }
+struct emu_v2u {
+  unsigned x, y;
+};
+inline emu_v2u __builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t r, int off, int soff, int) {
+  emu_v2u v;
+  __atomic_load((emu_v2u*)(r.base + off + soff), &v, __ATOMIC_SEQ_CST);
+  return v;
+}
+inline void __builtin_amdgcn_raw_buffer_store_b64(emu_v2u v, __amdgpu_buffer_rsrc_t r, int off, int soff, int) {
+  __atomic_store((emu_v2u*)(r.base + off + soff), &v, __ATOMIC_SEQ_CST);
 }
 // dynamic shared memory of the current workgroup (sized by the launch)
 inline thread_local std::vector<double> emu_dyn_lds;
@@ -172,7 +222,9 @@ void emu_entry(unsigned lo, unsigned hi) {
 template <class F>
 void emu_run_blocks(int b0, int step, int blocks, int threads, F& f, size_t dyn_lds_bytes) {
   constexpr size_t kStack = 512 * 1024;
-  std::vector<std::vector<char>> stacks(threads, std::vector<char>(kStack));
+  // fiber stacks left uninitialised: pages are committed only when used
+  std::vector<std::unique_ptr<char[]>> stacks(threads);
+  for (auto& st : stacks) st.reset(new char[kStack]);
   std::vector<char> done_store(threads);
   bool* done = (bool*)done_store.data();
   emu_task<F> task{&f, done};
@@ -180,11 +232,13 @@ void emu_run_blocks(int b0, int step, int blocks, int threads, F& f, size_t dyn_
   emu_dyn_lds.assign(dyn_lds_bytes / 8 + 1, 0.0);
   for (int b = b0; b < blocks; b += step) {
     blockIdx.x = b;
+    emu_blk_count = emu_blk_gen = 0;
+    for (int w = 0; w < 16; ++w) emu_wave_count[w] = emu_wave_gen[w] = 0;
     emu_lane_ctx.assign(threads, ucontext_t{});
     for (int t = 0; t < threads; ++t) {
       done[t] = false;
       getcontext(&emu_lane_ctx[t]);
-      emu_lane_ctx[t].uc_stack.ss_sp = stacks[t].data();
+      emu_lane_ctx[t].uc_stack.ss_sp = stacks[t].get();
       emu_lane_ctx[t].uc_stack.ss_size = kStack;
       emu_lane_ctx[t].uc_link = &emu_main_ctx;
       makecontext(&emu_lane_ctx[t], (void (*)())emu_entry<F>, 2, (unsigned)(p & 0xffffffffu), (unsigned)(p >> 32));

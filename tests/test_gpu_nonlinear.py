@@ -224,8 +224,3 @@ def test_state_and_argument_errors():
     with pytest.raises(native.AdiError) as e:
         p.set_laws(np.full(20, np.nan), np.ones(20), np.zeros(20))
     assert e.value.status == native.ADI_ENONFINITE
-    big = tiny_spec(7, 3100)
-    q = native.Problem.from_spec(big)
-    with pytest.raises(native.AdiError) as e:
-        q.set_laws(*laws_of(big))
-    assert e.value.status == native.ADI_EUNSUPPORTED

@@ -71,7 +71,9 @@ def nl_problem(s, laws):
 
 def run_emu(emu, tmp_path, s, laws, T, *, grid, mode, kind="const", pulse=PULSE, eps=1e-10, iter_max=10,
             tau_min=1e-14, div_trs=1000.0, div_src=100.0, ptol=0.0, t0=0.0, t_end_or_tau=1e-3,
-            max_steps=1 << 40, log_cap=0):
+            max_steps=1 << 40, log_cap=0, z_block=False):
+    """z_block: solve the z lines with a whole workgroup each (the long-line
+    path) instead of one wave each."""
     inp, out = tmp_path / "in.txt", tmp_path / "out.txt"
     fmt = lambda v: " ".join("%.17g" % x for x in np.ravel(v))
     faces = s.r_faces is not None
@@ -83,7 +85,10 @@ def run_emu(emu, tmp_path, s, laws, T, *, grid, mode, kind="const", pulse=PULSE,
                   eps, iter_max, tau_min, div_trs, div_src, ptol),
               "%.17g %.17g %d %d" % (t0, t_end_or_tau, min(max_steps, 1 << 60), log_cap), fmt(T)]
     inp.write_text("\n".join(lines) + "\n")
-    subprocess.run([str(emu), str(inp), str(out)], check=True, timeout=600)
+    env = dict(os.environ)
+    if z_block:
+        env["NL_EMU_WZ_BLOCK"] = "1"
+    subprocess.run([str(emu), str(inp), str(out)], check=True, timeout=600, env=env)
     rows = out.read_text().split("\n")
     h = rows[0].split()
     res = {"status": int(h[0]), "t": float(h[1]), "steps": int(h[2]), "rejected": int(h[3]),
@@ -95,9 +100,11 @@ def run_emu(emu, tmp_path, s, laws, T, *, grid, mode, kind="const", pulse=PULSE,
     return res
 
 
-def test_single_attempt_matches_oracle(emu, tmp_path):
+@pytest.mark.parametrize("z_block", [False, True], ids=["z_wave", "z_block"])
+def test_single_attempt_matches_oracle(emu, tmp_path, z_block):
     """One attempt at a fixed tau on a tiny grid with every face class: the
-    solves of each half step equal the oracle's, the field agrees to 1e-12."""
+    solves of each half step equal the oracle's, the field agrees to 1e-12;
+    z lines on one wave each and on a whole workgroup each."""
     s = tiny_spec(13, 31)
     laws = laws_of(s)
     P = nl_problem(s, laws)
@@ -106,7 +113,8 @@ def test_single_attempt_matches_oracle(emu, tmp_path):
         ok, want, its, chg = P.nl_step(T0, tau, 0.0, eps=1e-10, iter_max=30)
         assert ok and min(its) >= 3
         assert min(abs(c - 1e-10) / 1e-10 for c in chg) > 1e-3
-        got = run_emu(emu, tmp_path, s, laws, T0, grid=7, mode=1, eps=1e-10, iter_max=30, t_end_or_tau=tau)
+        got = run_emu(emu, tmp_path, s, laws, T0, grid=7, mode=1, eps=1e-10, iter_max=30, t_end_or_tau=tau,
+                      z_block=z_block)
         assert got["status"] == 4 and got["accepted"]
         assert got["it"] == its
         assert rel_inf(got["T"], want, P.active()) <= TOL
