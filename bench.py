@@ -278,6 +278,50 @@ def single_layout_leg():
     return out
 
 
+MLP_FLOP_PER_SAMPLE = 2 * (12 * 256 + 3 * 256 * 256 + 256 * 64)   # 432,128: the forward pass's products
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_leg(batch=65536, reps=50):
+    """Surrogate inference on the matrix cores: the 12 -> 4 x 256 GELU -> 64
+    network (bf16 operands, fp32 accumulation and output) over a batch of
+    `batch` seeded feature rows, `reps` forward passes timed with HIP events
+    on the network's stream; throughput in samples/s and the products'
+    rate against the dense bf16 MFMA peak (432,128 flops per sample)."""
+    import numpy as np
+    import torch
+
+    from paper_1912_03744_amd import native
+    from paper_1912_03744_amd import surrogate as S
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        net = native.MLP(S.WIDTHS, seed=5)
+        shift, scale = S.feature_scaling()
+        net.set_scaling(shift, scale)
+        rng = np.random.default_rng(0)
+        lo = np.concatenate([S.BOX_LO, [S.LOGT_LO]])
+        hi = np.concatenate([S.BOX_HI, [S.LOGT_HI]])
+        x = torch.tensor(rng.uniform(lo, hi, size=(batch, 12)).astype(np.float32), device="cuda")
+        y = torch.empty(batch, 64, device="cuda")
+        for _ in range(3):
+            net.forward(x, y)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            net.forward(x, y)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+    tflops = MLP_FLOP_PER_SAMPLE * batch / (ms * 1e-3) / 1e12
+    net.close()
+    return {"workload": "surrogate forward pass, 12 -> 4 x 256 (GELU) -> 64, bf16 matrix cores with fp32 "
+                        "accumulation, batch %d, seeded inputs over the design box" % batch,
+            "value": batch / (ms * 1e-3), "unit": "samples/s", "ms_per_batch": ms,
+            "roofline": {"bound": "mfma", "kernel": "k_layer (all layers)", "achieved": tflops,
+                         "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
+                         "traffic": None}}
+
+
 NL_BYTES_PER_CELL_SOLVE = 32  # per line solve: iterate, current layer and explicit part read, new iterate written
 
 
@@ -371,6 +415,9 @@ def main():
     ap.add_argument("--cpu-nonlinear-steps", type=int, default=400)
     ap.add_argument("--nonlinear-only", action="store_true",
                     help="run only the nonlinear case-study leg and print its figures")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="run only the surrogate inference leg and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -384,6 +431,9 @@ def main():
     from paper_1912_03744_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.surrogate_only:
+        print(json.dumps(surrogate_leg()), flush=True)
+        return
     if args.nonlinear_only:
         print(json.dumps(nonlinear_leg(args.nonlinear_t, args.cpu_nonlinear_steps, cpu=not args.no_cpu)),
               flush=True)
@@ -467,6 +517,10 @@ def main():
         print("bench: nonlinear %.3f s, %d steps, %.3e cell-updates/s" % (
             out["nonlinear"]["seconds"], out["nonlinear"]["steps"], out["nonlinear"]["value"]),
             file=sys.stderr, flush=True)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg()
+        print("bench: surrogate %.3e samples/s, %.1f TFLOP/s" % (out["surrogate"]["value"],
+              out["surrogate"]["roofline"]["achieved"]), file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps, args.cpu_threaded_steps)
         if "batch" in out:

@@ -46,7 +46,19 @@ struct GemmArgs {
   long split_stride;
 };
 
-__device__ __forceinline__ float gelu_f(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+// erf by the rational approximation of Abramowitz and Stegun, Handbook of
+// Mathematical Functions, formula 7.1.26 (|error| <= 1.5e-7, far below the
+// bf16 rounding of the activations it feeds): for x >= 0,
+// erf x = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x),
+// odd in x.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float r = 1.0f - poly * __expf(-ax * ax);
+  return copysignf(r, x);
+}
+__device__ __forceinline__ float gelu_f(float u) { return 0.5f * u * (1.0f + erf_as(u * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float u) {
   return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * 0.39894228040143268f * expf(-0.5f * u * u);
 }
@@ -120,14 +132,103 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   }
 }
 
-// x (B x nin fp32) -> (x - shift) * scale as bf16, zero-padded to KPAD columns.
+// One forward layer out = epilogue(A W + b) for a whole batch, with the
+// layer's weights resident in LDS: the workgroups stay for the whole batch
+// (one per compute unit), each first copies W^T (ND rows of KD bf16, rows
+// padded by 8 so that the 32 lanes reading one 16-byte column piece of 32
+// rows hit different banks), then takes row tiles of 64 NWAVE rows; each
+// wave multiplies its 64 rows (two 32-row A fragments per 16-wide k step,
+// held in registers for the whole K) with every 32-column block of W^T,
+// reusing each W fragment for both row halves: 2 ND/32 accumulators of
+// 32 x 32 fp32.  The k steps run in the same order as in k_gemm, so each
+// output element sees the same sequence of products and sums.
+template <int KD, int ND, int EPI>
+__global__ void __launch_bounds__(256) k_layer(const __bf16* __restrict__ A, const __bf16* __restrict__ Wt,
+                                               const float* __restrict__ bias, long B, float* out_f32,
+                                               __bf16* out_bf16) {
+  constexpr int NWAVE = 4, ROWS = 64 * NWAVE, LDW = KD + 8, NB = ND / 32, KS = KD / 16;
+  __shared__ __attribute__((aligned(16))) __bf16 W[ND * LDW];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  // W^T into LDS: ND x KD bf16 in 16-byte pieces
+  for (int q = t; q < ND * KD / 8; q += 256) {
+    const int n = q / (KD / 8), k8 = q % (KD / 8);
+    *(bf16x8*)&W[n * LDW + 8 * k8] = *(const bf16x8*)(Wt + (long)n * KD + 8 * k8);
+  }
+  __syncthreads();
+  const int half = lane >> 5, lr = lane & 31;
+  for (long tile = blockIdx.x; tile * ROWS < B; tile += gridDim.x) {
+    const long m0 = tile * ROWS + wave * 64;
+    // the wave's A fragments: rows m0 + lr (first half) and m0 + 32 + lr
+    bf16x8 a0[KS], a1[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const long r0 = m0 + lr, r1 = m0 + 32 + lr;
+      bf16x8 z;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+      a0[k] = r0 < B ? *(const bf16x8*)(A + r0 * KD + 16 * k + 8 * half) : z;
+      a1[k] = r1 < B ? *(const bf16x8*)(A + r1 * KD + 16 * k + 8 * half) : z;
+    }
+    floatx16 acc0[NB], acc1[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        acc0[nb][i] = 0.0f;
+        acc1[nb][i] = 0.0f;
+      }
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const bf16x8 b = *(const bf16x8*)&W[(nb * 32 + lr) * LDW + 16 * k + 8 * half];
+        acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[k], b, acc0[nb], 0, 0, 0);
+        acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[k], b, acc1[nb], 0, 0, 0);
+      }
+    // epilogue: accumulator i of lane l holds row 8 (i/4) + 4 (l/32) + i%4,
+    // column l%32 of its 32 x 32 block (32 lanes store 32 consecutive
+    // columns of a row: 64-byte runs in bf16; packing 4 values per lane
+    // along the accumulator index instead, by swapping the operands, scatters
+    // 8-byte pieces over 32 rows and was measured twice as slow)
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int n = nb * 32 + lr;
+        const float bn = bias[n];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const long m = m0 + 32 * hb + 8 * (i >> 2) + 4 * half + (i & 3);
+          if (m >= B) continue;
+          const float v = hb ? acc1[nb][i] : acc0[nb][i];
+          const long o = m * ND + n;
+          const float u = v + bn;
+          if constexpr (EPI == EPI_OUTPUT) {
+            out_f32[o] = u;
+          } else {
+            if constexpr (EPI == EPI_HIDDEN) out_f32[o] = u;
+            out_bf16[o] = (__bf16)gelu_f(u);
+          }
+        }
+      }
+  }
+}
+
+// x (B x nin fp32) -> (x - shift) * scale as bf16, zero-padded to KPAD
+// columns: one row per thread, written as KPAD/8 16-byte pieces.
 __global__ void k_encode(const float* __restrict__ x, int nin, long B, const float* shift, const float* scale,
                          __bf16* __restrict__ out) {
-  const long n = B * KPAD;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const long r = e / KPAD;
-    const int c = (int)(e % KPAD);
-    out[e] = (__bf16)(c < nin ? (x[r * nin + c] - shift[c]) * scale[c] : 0.0f);
+  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < B; r += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int p = 0; p < KPAD / 8; ++p) {
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int c = 8 * p + e;
+        v[e] = (__bf16)(c < nin ? (x[r * nin + c] - shift[c]) * scale[c] : 0.0f);
+      }
+      *(bf16x8*)(out + r * KPAD + 8 * p) = v;
+    }
   }
 }
 
@@ -252,6 +353,7 @@ void* noalloc_scratch_ptr(int dev) {
 
 struct adi_mlp_s {
   int device = 0;
+  int cus = 256;              // compute units of the device
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int nl = 0;                 // number of weight layers
@@ -354,62 +456,38 @@ adi_status check_batch(adi_mlp m, long B) {
   return ADI_OK;
 }
 
-// Inference-only forward pass: encoded input in X, hidden activations
-// alternating between H0 and H1 (no pre-activations kept), output straight
-// into y.  The same products and epilogue arithmetic as forward().
-adi_status forward_infer(adi_mlp m, const float* x, long B, __bf16* X, __bf16* H0, __bf16* H1, float* y) {
-  hipLaunchKernelGGL(k_encode, dim3((int)std::min<long>((B * KPAD + 255) / 256, 8192)), dim3(256), 0, m->stream,
+adi_status layer_forward(adi_mlp m, int l, int epi, const __bf16* in, long B, float* of, __bf16* ob);
+
+// Inference-only forward pass: encoded input in X, hidden activations of
+// layer l in H[l] (no pre-activations kept), output straight into y.  The
+// same products and epilogue arithmetic as forward().
+adi_status forward_infer(adi_mlp m, const float* x, long B, __bf16* X, __bf16* const* H, float* y) {
+  hipLaunchKernelGGL(k_encode, dim3((int)std::min<long>((B + 255) / 256, 8192)), dim3(256), 0, m->stream,
                      x, m->width[0], B, m->shift, m->scale, X);
   ADI_CHECK_LAUNCH();
   const __bf16* in = X;
   for (int l = 0; l < m->nl; ++l) {
-    GemmArgs g{};
-    g.A = in;
-    g.lda = m->kin_pad[l];
-    g.B = m->Wtb[l];
-    g.ldb = m->kin_pad[l];
-    g.M = (int)B;
-    g.N = m->width[l + 1];
-    g.K = g.Ks = m->kin_pad[l];
-    g.bias = m->P + m->boff[l];
-    g.ldo = m->width[l + 1];
     if (l < m->nl - 1) {
-      __bf16* out = (l & 1) ? H1 : H0;
-      g.out_bf16 = out;
-      ADI_TRY((gemm<true, true, EPI_INFER>(m, g, 1)));
-      in = out;
+      ADI_TRY(layer_forward(m, l, EPI_INFER, in, B, nullptr, H[l]));
+      in = H[l];
     } else {
-      g.out_f32 = y;
-      ADI_TRY((gemm<true, true, EPI_OUTPUT>(m, g, 1)));
+      ADI_TRY(layer_forward(m, l, EPI_OUTPUT, in, B, y, nullptr));
     }
   }
   return ADI_OK;
 }
 
 adi_status forward(adi_mlp m, const float* x, long B) {
-  hipLaunchKernelGGL(k_encode, dim3((int)std::min<long>((B * KPAD + 255) / 256, 8192)), dim3(256), 0, m->stream,
+  hipLaunchKernelGGL(k_encode, dim3((int)std::min<long>((B + 255) / 256, 8192)), dim3(256), 0, m->stream,
                      x, m->width[0], B, m->shift, m->scale, m->X);
   ADI_CHECK_LAUNCH();
   const __bf16* in = m->X;
   for (int l = 0; l < m->nl; ++l) {
-    GemmArgs g{};
-    g.A = in;
-    g.lda = m->kin_pad[l];
-    g.B = m->Wtb[l];
-    g.ldb = m->kin_pad[l];
-    g.M = (int)B;
-    g.N = m->width[l + 1];
-    g.K = g.Ks = m->kin_pad[l];
-    g.bias = m->P + m->boff[l];
-    g.ldo = m->width[l + 1];
     if (l < m->nl - 1) {
-      g.out_f32 = m->U[l];
-      g.out_bf16 = m->H[l];
-      ADI_TRY((gemm<true, true, EPI_HIDDEN>(m, g, 1)));
+      ADI_TRY(layer_forward(m, l, EPI_HIDDEN, in, B, m->U[l], m->H[l]));
       in = m->H[l];
     } else {
-      g.out_f32 = m->Y;
-      ADI_TRY((gemm<true, true, EPI_OUTPUT>(m, g, 1)));
+      ADI_TRY(layer_forward(m, l, EPI_OUTPUT, in, B, m->Y, nullptr));
     }
   }
   return ADI_OK;
@@ -483,6 +561,47 @@ adi_status backward(adi_mlp m, const float* target, long B) {
   return ADI_OK;
 }
 
+// One forward layer through k_layer when its (padded) input and output
+// widths are ones it is built for, else through k_gemm.  epi: EPI_HIDDEN,
+// EPI_INFER or EPI_OUTPUT.
+template <int KD, int ND>
+adi_status launch_layer(adi_mlp m, int epi, const __bf16* A, const __bf16* Wt, const float* bias, long B,
+                        float* of, __bf16* ob) {
+  const int grid = (int)std::min<long>(m->cus, (B + 255) / 256);
+  if (epi == EPI_HIDDEN)
+    hipLaunchKernelGGL((k_layer<KD, ND, EPI_HIDDEN>), dim3(grid), dim3(256), 0, m->stream, A, Wt, bias, B, of, ob);
+  else if (epi == EPI_INFER)
+    hipLaunchKernelGGL((k_layer<KD, ND, EPI_INFER>), dim3(grid), dim3(256), 0, m->stream, A, Wt, bias, B, of, ob);
+  else
+    hipLaunchKernelGGL((k_layer<KD, ND, EPI_OUTPUT>), dim3(grid), dim3(256), 0, m->stream, A, Wt, bias, B, of, ob);
+  ADI_CHECK_LAUNCH();
+  return ADI_OK;
+}
+
+adi_status layer_forward(adi_mlp m, int l, int epi, const __bf16* in, long B, float* of, __bf16* ob) {
+  const int kd = m->kin_pad[l], nd = m->width[l + 1];
+  const float* bias = m->P + m->boff[l];
+  if (kd == 64 && nd == 256) return launch_layer<64, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (kd == 256 && nd == 256) return launch_layer<256, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (kd == 256 && nd == 64) return launch_layer<256, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (kd == 64 && nd == 64) return launch_layer<64, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  GemmArgs g{};
+  g.A = in;
+  g.lda = kd;
+  g.B = m->Wtb[l];
+  g.ldb = kd;
+  g.M = (int)B;
+  g.N = nd;
+  g.K = g.Ks = kd;
+  g.bias = bias;
+  g.ldo = nd;
+  g.out_f32 = of;
+  g.out_bf16 = ob;
+  if (epi == EPI_HIDDEN) return gemm<true, true, EPI_HIDDEN>(m, g, 1);
+  if (epi == EPI_INFER) return gemm<true, true, EPI_INFER>(m, g, 1);
+  return gemm<true, true, EPI_OUTPUT>(m, g, 1);
+}
+
 }  // namespace
 
 extern "C" {
@@ -517,6 +636,8 @@ adi_status adi_mlp_create(const int32_t* widths, int32_t nwidths, uint64_t seed,
   if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
   adi_status st = noalloc_scratch_setup(m->device);
   if (st != ADI_OK) return cleanup(st);
+  e = hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, m->device);
+  if (e != hipSuccess) return cleanup(fail(ADI_EDEVICE, "device attribute: %s", hipGetErrorString(e)));
   m->stream = (hipStream_t)hip_stream;
   if (!m->stream) {
     e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
@@ -602,8 +723,8 @@ adi_status adi_mlp_forward(adi_mlp m, const float* dev_x, int64_t batch, float* 
   if (!dev_x || !dev_y) return fail(ADI_EINVAL, "null device buffer");
   ADI_TRY(check_batch(m, batch));
   ADI_TRY(ensure_acts(m, batch));
-  ADI_TRY(forward(m, dev_x, batch));
-  ADI_HIP(hipMemcpyAsync(dev_y, m->Y, 4 * batch * m->width[m->nl], hipMemcpyDeviceToDevice, m->stream));
+  // inference only: no pre-activations kept, the output straight into dev_y
+  ADI_TRY(forward_infer(m, dev_x, batch, m->X, m->H, dev_y));
   return ADI_OK;
 }
 
@@ -623,7 +744,9 @@ adi_status adi_mlp_forward_noalloc(adi_mlp m, const float* dev_x, int64_t batch,
                 (long)ADI_MLP_NOALLOC_SCRATCH_BYTES / per_row / BM * BM);
   unsigned char* base = (unsigned char*)noalloc_scratch_ptr(m->device);
   if (!base) return fail(ADI_EDEVICE, "work area of device %d was not set up", m->device);
-  return forward_infer(m, dev_x, batch, (__bf16*)base, (__bf16*)(base + xb), (__bf16*)(base + xb + hb), dev_y);
+  __bf16* H[MAX_LAYERS];
+  for (int l = 0; l < MAX_LAYERS; ++l) H[l] = (__bf16*)(base + xb + (l & 1) * hb);
+  return forward_infer(m, dev_x, batch, (__bf16*)base, H, dev_y);
 }
 
 adi_status adi_mlp_sync(adi_mlp m) {

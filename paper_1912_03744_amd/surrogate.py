@@ -360,6 +360,9 @@ def _run(n_train, n_val, n_test, n_sweep, top_frac, epochs, n_recall, n_plain, l
     res["sweep"]["gain_vs_plain"] = (n_sweep / t_screened) * t_plain
     res["sweep"]["gain_vs_batched_only"] = (n_sweep / t_screened) / (n_recall / t_batched)
     log("sweep %s" % res["sweep"])
+    # arrays for callers that check the pipeline (not part of the JSON report)
+    res["_selected"] = {"designs": Dsw[top], "profiles": Ptop, "predicted_peak": peak_pred[top],
+                        "recall_truth": truth, "recall_pred": peak_pred[sub]}
     res["total_seconds"] = time.perf_counter() - t_all
     return res
 
@@ -386,7 +389,7 @@ def main():
 
     res = run(n_train=a.n_train, n_val=a.n_val, n_test=a.n_test, n_sweep=a.n_sweep, epochs=a.epochs,
               n_recall=a.n_recall, n_plain=a.n_plain, log=log)
-    txt = json.dumps(res, indent=1)
+    txt = json.dumps({k: v for k, v in res.items() if not k.startswith("_")}, indent=1)
     if a.out:
         with open(a.out, "w") as f:
             f.write(txt)

@@ -1,9 +1,19 @@
 """End-to-end surrogate path at a small scale: labels from the batched FP64
 solver, ensemble training on the matrix-core kernels, gate calibration, the
 held-out judgement and the screened sweep against the plain and batched
-solvers.  Checks the bookkeeping and what the network buys: the screened
-sweep evaluates designs faster than the plain per-instance solver, and its
-selected designs come back with FP64 solver values."""
+solvers.
+
+Checks, beyond the bookkeeping:
+  * the designs the screened sweep re-solves come back with the FP64
+    solver's values: three of the selected designs are solved again by the
+    oracle (5000 steps of 4e-4 on 128 x 320) and their terminal-face
+    profiles agree with the pipeline's to 1e-12;
+  * the network ranks: its top 1 % of a fully solved subset recovers at
+    40 % of the true top 1 % (random selection recovers 1 % on
+    average; the trained network at full scale recovers 98 %), and its peak
+    predictions correlate with the solver's (Spearman >= 0.9 on the subset);
+  * the screened sweep evaluates designs faster than the plain per-instance
+    solver."""
 import numpy as np
 import pytest
 
@@ -13,17 +23,31 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="n
 
 
 def test_screened_sweep_small():
+    import oracle
     from paper_1912_03744_amd import surrogate as S
-    res = S.run(n_train=768, n_val=256, n_test=256, n_sweep=8192, n_recall=1024, epochs=4, n_plain=3,
+    from paper_1912_03744_amd import workloads as W
+    res = S.run(n_train=4096, n_val=512, n_test=256, n_sweep=16384, n_recall=4096, epochs=12, n_plain=3,
                 log=lambda m: print(m, flush=True))
-    h, sw = res["heldout"], res["sweep"]
-    print(res, flush=True)
+    h, sw, sel = res["heldout"], res["sweep"], res["_selected"]
+    print({k: v for k, v in res.items() if not k.startswith("_")}, flush=True)
     assert 0.0 <= h["gate_pass_rate"] <= 1.0
     # the calibrated gate never keeps a validation design above the target
     assert res["calibration"]["delta"] >= 0.0
     if h["max_err_passed"] is not None:
         assert np.isfinite(h["max_err_passed"])
-    assert sw["selected"] == 82 and 0.0 <= sw["recall_at_top"] <= 1.0
-    assert -1.0 <= sw["spearman_selected"] <= 1.0
+    assert sw["selected"] == 164 and len(sel["designs"]) == 164
+    # ranking quality on the fully solved subset
+    assert sw["recall_at_top"] >= 0.4, sw["recall_at_top"]
+    assert S.spearman(sel["recall_pred"], sel["recall_truth"]) >= 0.9
+    # the re-solved selected designs carry FP64 solver values
+    for i in (0, 81, 163):
+        spec = W.design_spec(W.design_from_row(sel["designs"][i]), *S.LABEL_GRID, dt=4e-4, nsteps=5000)
+        P = oracle.Problem.from_spec(spec)
+        T, _ = P.step_threads(P.initial(spec.T0), "pr", 4e-4, 5000, 16)
+        want = P.profile(T, 0, S.NPTS)
+        got = sel["profiles"][i]
+        err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        print("selected design %d: profile rel err %.2e vs oracle" % (i, err), flush=True)
+        assert err <= 1e-12
     # what the surrogate gains: screened designs/s beat the plain solver
     assert sw["designs_per_s_screened"] > sw["designs_per_s_plain"]
