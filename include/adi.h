@@ -58,8 +58,16 @@ typedef enum { ADI_PR = 0, ADI_LOD_BE = 1 } adi_scheme;
  *   ADI_LAYOUT_ROWS    by rows, like T; any grid size;
  *   ADI_LAYOUT_STRIPS  strips of 4 columns, each strip a contiguous run of
  *                      rows of 4 values, so that both sweeps move whole
- *                      cache lines; nr <= 2048 and nz <= 3072. */
-typedef enum { ADI_LAYOUT_ROWS = 0, ADI_LAYOUT_STRIPS = 1 } adi_layout;
+ *                      cache lines; nr <= 2048 and nz <= 3072;
+ *   ADI_LAYOUT_RESIDENT  by rows between calls, but every run of steps
+ *                      between energy checks runs in one launch of a single
+ *                      workgroup that keeps the right-hand side in LDS (lines
+ *                      solved by two-ended Thomas elimination, two lanes per
+ *                      line); for small grids: 3 <= nr, nz <= 512 and
+ *                      nz (nr + 1) + 8 (3 nr + 4 nz) doubles within 160 KB
+ *                      (64 x 160 takes 136 KB).  Check steps run on the rows
+ *                      kernels. */
+typedef enum { ADI_LAYOUT_ROWS = 0, ADI_LAYOUT_STRIPS = 1, ADI_LAYOUT_RESIDENT = 2 } adi_layout;
 
 /* Geometry of Fig. 1 (Sec. 2): cooler r < r0 for z < zmax; inner insulator
  * r0 <= r < r1, heater r1 <= r < r2, outer insulator r2 <= r < rmax, all three
@@ -159,8 +167,10 @@ adi_status adi_energy(adi_problem p, adi_energy_report* out);
  * then z sweep, each reading what the other has just written, as in a time
  * step) on the problem's side buffers and stream, every launch carrying HIP
  * start and end events of its own dispatch; returns the mean duration per
- * launch of each direction in ms.  The field and the carried right-hand side are left
- * unchanged.  Synchronises. */
+ * launch of each direction in ms.  Under ADI_LAYOUT_RESIDENT: nlaunch steps
+ * in one launch on a copy of the carried right-hand side, *ms_r = the time per
+ * step (launch included) and *ms_z = 0.  The field and the carried
+ * right-hand side are left unchanged.  Synchronises. */
 adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_r, float* ms_z);
 
 /* Launch shape of the line solves (advanced; the autotuner uses it).
@@ -183,7 +193,9 @@ adi_status adi_get_launch(adi_problem p, int32_t dir, int32_t* chunk, int32_t* l
 adi_status adi_launch_shapes(int32_t* out, int32_t max_shapes, int32_t* count);
 
 /* Same for a layout and direction (dir 0 = r, 1 = z).  Strip-layout shapes
- * are (chunk, 1, waves, 4, 1): one line slot per wave, 4 lines per lane. */
+ * are (chunk, 1, waves, 4, 1): one line slot per wave, 4 lines per lane.
+ * ADI_LAYOUT_RESIDENT has one fixed shape and lists none (*count = 0); its
+ * check steps use the rows shapes set with adi_set_launch. */
 adi_status adi_layout_shapes(int32_t layout, int32_t dir, int32_t* out, int32_t max_shapes, int32_t* count);
 
 /* Choose the right-hand-side layout (adi_layout); resets both launch shapes

@@ -4,8 +4,9 @@ Single problems: for each right-hand-side layout (rows, strips of 4
 columns) and sweep direction it times every compiled launch shape (cells per
 chunk, lines per wave, waves per line, lines per lane, groups per workgroup)
 that covers the line length without too much padding, using
-adi_time_sweeps (HIP events on the problem's stream), and keeps the layout
-and shapes with the smallest time per step.  Ragged batches: it times the persistent batch kernel (lines per
+adi_time_sweeps (HIP events on the problem's stream); grids small enough for
+the LDS-resident time loop time it too (a run of steps in one launch, per
+step); it keeps the layout and shapes with the smallest time per step.  Ragged batches: it times the persistent batch kernel (lines per
 lane, waves per workgroup, resident workgroups per compute unit) on a short
 run of the batch itself with adi_batch_time.  Results are cached in a JSON
 file keyed by GPU architecture, problem size (or the batch's size mix) and
@@ -94,6 +95,19 @@ def _tune_layout(problem, dt, layout, nlaunch, reps, verbose, log):
     return res
 
 
+def _time_resident(problem, dt, nlaunch, reps, verbose, log):
+    """Time per step of the LDS-resident loop (the whole step, launch
+    included, so that it is never favoured over the sweep kernels' own
+    durations); its shapes are the rows defaults its check steps use."""
+    steps = max(nlaunch, 200)
+    t = min(problem.time_sweeps(dt, steps)[0] for _ in range(reps))
+    if verbose:
+        msg = "autotune resident: %.4f ms per step" % t
+        print(msg, flush=True) if log is None else log(msg)
+    return {"trials": [{"layout": "resident", "dir": None, "shape": None, "ms": t}],
+            "r": (problem.get_launch(0), t), "z": (problem.get_launch(1), 0.0)}
+
+
 def tune(problem, dt, nlaunch=20, reps=2, verbose=False, log=None):
     """Time every candidate shape of every layout in both directions and set
     the layout and shapes with the smallest r + z time.  Returns {"layout":
@@ -104,7 +118,10 @@ def tune(problem, dt, nlaunch=20, reps=2, verbose=False, log=None):
             problem.set_layout(layout)
         except native.AdiError:
             continue
-        res = _tune_layout(problem, dt, layout, nlaunch, reps, verbose, log)
+        if layout == "resident":
+            res = _time_resident(problem, dt, nlaunch, reps, verbose, log)
+        else:
+            res = _tune_layout(problem, dt, layout, nlaunch, reps, verbose, log)
         if res is None:
             continue
         trials += res["trials"]

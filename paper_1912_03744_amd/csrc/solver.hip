@@ -9,6 +9,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,6 +22,7 @@
 #include "common.hpp"
 #include "device.hpp"
 #include "strip.hpp"
+#include "resident.hpp"
 #include "problem_core.hpp"
 
 namespace adi {
@@ -718,6 +720,53 @@ bool is_check_step(const adi_problem p, int64_t global_step) {
 }
 
 // Enqueue one step.  write_T: the z sweep also stores the solution in T.
+// The LDS-resident kernel runs grids whose lines split into chunks of at
+// most 16 cells over its waves and whose right-hand side and tables fit in
+// the 160 KB of LDS of one compute unit.
+bool resident_fits(int nr, int nz) {
+  return resident_shape_ok(nr, nz) && resident_lds_doubles(nr, nz) * 8 <= 160L * 1024;
+}
+
+// n steps of the LDS-resident kernel (launches of at most 2^20 steps) from
+// the carried right-hand side in rhs (rows layout), which it leaves carried
+// again; T (if not null) receives the field after the last step.  e0 / e1:
+// start and end events of the first and last launch (null: none).
+adi_status launch_resident(adi_problem p, double* rhs, double* T, int64_t n, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr) {
+  // the kernel takes more than the default 64 KB of dynamic LDS: raise its
+  // limit once per device
+  static std::atomic<uint64_t> attr_set{0};
+  const uint64_t bit = p->device < 64 ? 1ull << p->device : 0;
+  if (!bit || !(attr_set.load() & bit)) {
+    ADI_HIP(hipFuncSetAttribute((const void*)k_resident, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_set.fetch_or(bit);
+  }
+  const size_t lds = sizeof(double) * resident_lds_doubles(p->P.nr, p->P.nz);
+  bool ambient = false;
+  for (int c = 0; c < 4; ++c) ambient = ambient || p->P.tinf[c] != 0.0;
+  for (int64_t done = 0; done < n;) {
+    const int k = (int)std::min<int64_t>(n - done, 1 << 20);
+    ResArgs a;
+    a.P = p->P;
+    a.g = p->g;
+    a.rhs = rhs;
+    a.T = T;
+    a.xcr = ambient ? p->r.xc : nullptr;  // the z sweep adds b_r
+    a.xcz = ambient ? p->z.xc : nullptr;  // the r sweep adds b_z
+    a.nsteps = k;
+    a.write_T = T && done + k == n;
+    void* args[] = {&a};
+    hipEvent_t s0 = done == 0 ? e0 : nullptr, s1 = done + k == n ? e1 : nullptr;
+    if (s0 || s1)
+      (void)hipExtLaunchKernel((const void*)k_resident, dim3(1), dim3(RES_THREADS), args, lds, p->stream, s0, s1, 0);
+    else
+      (void)hipLaunchKernel((const void*)k_resident, dim3(1), dim3(RES_THREADS), args, lds, p->stream);
+    ADI_CHECK_LAUNCH();
+    done += k;
+  }
+  return ADI_OK;
+}
+
 adi_status enqueue_step(adi_problem p, bool check, bool write_T) {
   if (check) ADI_TRY(launch_energy(p, p->T, p->eout));
   ADI_TRY(launch_sweep(p, 0, p->dA, p->dB, check ? p->mid : nullptr));
@@ -842,6 +891,32 @@ adi_status validate_bc(const adi_bc* bc) {
     if (!(bc->h[c] >= 0.0) || bc->h[c] != bc->h[c]) return fail(ADI_EINVAL, "h[%d] must be >= 0", c);
     if (!is_fin(bc->t_inf[c])) return fail(ADI_EINVAL, "t_inf[%d] must be finite", c);
   }
+  return ADI_OK;
+}
+
+// The resident layout's timing: nlaunch steps in one launch on a copy of
+// the carried right-hand side (in mid); the time per step.
+adi_status time_resident(adi_problem p, int32_t nlaunch, float* ms_step, float* ms_zero) {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  adi_status st = ADI_OK;
+  for (auto& x : e)
+    if (hipEventCreate(&x) != hipSuccess) {
+      x = nullptr;
+      st = fail(ADI_EDEVICE, "hipEventCreate failed");
+    }
+  if (st == ADI_OK && hipMemcpyAsync(p->mid, p->dA, sizeof(double) * p->P.nr * p->P.nz, hipMemcpyDeviceToDevice,
+                                     p->stream) != hipSuccess)
+    st = fail(ADI_EDEVICE, "copy of the carried right-hand side failed");
+  if (st == ADI_OK) st = launch_resident(p, p->mid, nullptr, nlaunch, e[0], e[1]);
+  hipError_t err = hipStreamSynchronize(p->stream);
+  float ms = 0.f;
+  if (st == ADI_OK && err == hipSuccess) err = hipEventElapsedTime(&ms, e[0], e[1]);
+  for (auto& x : e)
+    if (x) (void)hipEventDestroy(x);
+  if (st != ADI_OK) return st;
+  if (err != hipSuccess) return fail(ADI_EDEVICE, "event timing: %s", hipGetErrorString(err));
+  if (ms_step) *ms_step = ms / nlaunch;
+  if (ms_zero) *ms_zero = 0.f;
   return ADI_OK;
 }
 
@@ -1078,6 +1153,28 @@ adi_status adi_step(adi_problem p, double dt, int64_t nsteps) {
   if (!p->rhs_valid) ADI_TRY(launch_init_rhs(p));
   int64_t s = 0;
   const int K = p->graph_steps;
+  if (p->layout == ADI_LAYOUT_RESIDENT) {
+    // every run of steps between checks in one launch; a check step on the
+    // rows kernels
+    while (s < nsteps) {
+      const int64_t gs = p->steps + s;
+      int64_t seg = nsteps - s;
+      if (p->check_every > 0) {
+        const int64_t to_next = p->check_every - (gs % p->check_every);
+        seg = std::min<int64_t>(seg, is_check_step(p, gs) ? p->check_every : to_next);
+      }
+      int64_t left = seg;
+      if (is_check_step(p, gs)) {
+        ADI_TRY(enqueue_step(p, true, seg == 1));
+        left -= 1;
+      }
+      if (left > 0) ADI_TRY(launch_resident(p, p->dA, p->T, left));
+      s += seg;
+    }
+    p->steps += nsteps;
+    p->time += dt * (double)nsteps;
+    return ADI_OK;
+  }
   while (s < nsteps) {
     const int64_t gs = p->steps + s;
     const int64_t left = nsteps - s;
@@ -1195,6 +1292,7 @@ adi_status adi_time_sweeps(adi_problem p, double dt, int32_t nlaunch, float* ms_
   if (!(dt > 0.0)) return fail(ADI_EINVAL, "dt must be > 0");
   ADI_TRY(ensure_tables(p, dt));
   if (!p->rhs_valid) ADI_TRY(launch_init_rhs(p));
+  if (p->layout == ADI_LAYOUT_RESIDENT) return time_resident(p, nlaunch, ms_r, ms_z);
   // Half steps alternate as in a time step, so every sweep reads what the
   // other direction has just written: r sweeps read the last z output (dA
   // first) and write dB, z sweeps read dB and write mid; the carried state
@@ -1263,9 +1361,11 @@ adi_status adi_sync(adi_problem p) {
 
 adi_status adi_set_layout(adi_problem p, int32_t layout) {
   ADI_TRY(check_handle(p));
-  if (layout != ADI_LAYOUT_ROWS && layout != ADI_LAYOUT_STRIPS)
+  if (layout != ADI_LAYOUT_ROWS && layout != ADI_LAYOUT_STRIPS && layout != ADI_LAYOUT_RESIDENT)
     return fail(ADI_EINVAL, "unknown layout %d", (int)layout);
   if (layout == p->layout) return ADI_OK;
+  if (layout == ADI_LAYOUT_RESIDENT && !resident_fits(p->P.nr, p->P.nz))
+    return fail(ADI_EUNSUPPORTED, "grid %dx%d does not fit the LDS-resident kernel", p->P.nr, p->P.nz);
   Launch Lr, Lz;
   if (layout == ADI_LAYOUT_STRIPS) {
     if (!default_strip_launch(0, p->P.nr, &Lr) || !default_strip_launch(1, p->P.nz, &Lz))
@@ -1300,6 +1400,10 @@ adi_status adi_layout_shapes(int32_t layout, int32_t dir, int32_t* out, int32_t 
   if (max_shapes > 0 && !out) return fail(ADI_EINVAL, "null output array");
   if (dir != 0 && dir != 1) return fail(ADI_EINVAL, "dir must be 0 (r) or 1 (z)");
   if (layout == ADI_LAYOUT_ROWS) return adi_launch_shapes(out, max_shapes, count);
+  if (layout == ADI_LAYOUT_RESIDENT) {
+    *count = 0;  // one fixed launch shape
+    return ADI_OK;
+  }
   if (layout != ADI_LAYOUT_STRIPS) return fail(ADI_EINVAL, "unknown layout %d", (int)layout);
   int c = 0;
   for (int v = 0; v < kNumStrip; ++v) {

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libadi.so")
 ADI_OK, ADI_EINVAL, ADI_ENOMEM, ADI_EDEVICE, ADI_ESTATE = 0, -1, -2, -3, -4
 ADI_ENONFINITE, ADI_EBALANCE, ADI_EUNSUPPORTED = -5, -6, -7
 SCHEMES = {"pr": 0, "lod": 1}
-LAYOUTS = {"rows": 0, "strips": 1}
+LAYOUTS = {"rows": 0, "strips": 1, "resident": 2}
 
 
 class AdiError(RuntimeError):
@@ -360,7 +360,8 @@ class Problem:
         return out
 
     def set_layout(self, layout):
-        """"rows" or "strips" (adi_set_layout); resets the launch shapes."""
+        """"rows", "strips" or "resident" (adi_set_layout); resets the launch
+        shapes."""
         check(lib().adi_set_layout(self._h, LAYOUTS[layout]))
 
     def layout(self):
@@ -578,8 +579,8 @@ def launch_shapes():
 
 
 def layout_shapes(layout, direction):
-    """Compiled launch shapes of a layout ("rows" or "strips") for one
-    direction (0 = r, 1 = z)."""
+    """Compiled launch shapes of a layout ("rows" or "strips"; "resident" has
+    one fixed shape and lists none) for one direction (0 = r, 1 = z)."""
     n = ctypes.c_int32()
     check(lib().adi_layout_shapes(LAYOUTS[layout], int(direction), None, 0, ctypes.byref(n)))
     buf = (ctypes.c_int32 * max(1, 5 * n.value))()
