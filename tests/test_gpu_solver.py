@@ -276,6 +276,32 @@ def test_nonuniform_layer_aligned_grid():
     assert np.array_equal(p.region_map(), P.region_map())
 
 
+@pytest.mark.parametrize("scheme", ["lod", "pr"])
+def test_case_study_grid_linear(scheme):
+    """The case-study grid of Sec. 5 through the face arrays (per-layer
+    uniform faces, 800/200/200/10 x 80/20 cells, widths down to 1e-5 against
+    0.05 in z), T0 held on the top face (Dirichlet, eq. 6), insulated
+    elsewhere, constant coefficients with a heater source: 200 steps of 1e-4.
+    The coating cells couple about 1e6 times more strongly than their
+    capacity term (tau k / (dr^2 rho c)), so both schemes are held to the
+    rounding bound stiff_tol (see test_nonlinear_emulation.py) instead of
+    1e-12: two correct line solvers differ by about eps times that ratio
+    per solve, Peaceman-Rachford's explicit half adds the same amount, and
+    with weights tau / 2 (PR) or tau (LOD backward Euler) per half step the
+    bound is 4 eps sum(weight * max coupling ratio).  Measured: about 1e-11
+    against bounds near 1e-7."""
+    from test_nonlinear_emulation import stiff_tol
+    s = W.case_study().replace(scheme=scheme)
+    _say("case-study grid %dx%d linear %s" % (s.nr, s.nz, scheme))
+    P, want, _ = run_oracle(s, 200)
+    p, got = run_gpu(s, 200)
+    tol = stiff_tol(P, [s.dt if scheme == "pr" else 2 * s.dt] * 200, 1.0)
+    err = rel_inf(got, want, P.active())
+    _say("case-study grid %s: rel err %.2e (bound %.2e)" % (scheme, err, tol))
+    assert err <= tol
+    assert np.max(np.abs(want[P.active()] - s.T0)) > 1e-6  # the heater has warmed the cell
+
+
 def test_set_field_and_continuation():
     """Stepping 3 + 4 equals stepping 7; a host field is accepted; changing
     dt rebuilds the tables."""
