@@ -9,16 +9,22 @@
 // so nothing is factored ahead of time: each iteration assembles the
 // coefficients of its lines from the current iterate and solves them.  The
 // whole time loop runs in one persistent cooperative launch (every
-// workgroup resident), one wave per workgroup:
+// workgroup resident, NW waves each):
 //
-//   * a wave takes one line at a time (row of the r half step, column of the
-//     z half step), stages its iterate, current layer and explicit part in
-//     LDS, assembles the tridiagonal row of every cell of the line and solves
-//     the line by a partition method computed on the fly: each lane
-//     eliminates a chunk of consecutive cells (Thomas with two spike
-//     columns), the chunk-end unknowns form a reduced tridiagonal system of
-//     one row per lane, solved by parallel cyclic reduction over wavefront
-//     shuffles, then the lane substitutes back;
+//   * a workgroup takes one row of the r half step at a time (all its NW
+//     waves on the row), a wave one column of the z half step (or the whole
+//     workgroup, for columns longer than 16 cells per lane), stages the
+//     line's iterate, current layer and explicit part in LDS, assembles the
+//     tridiagonal row of every cell and solves the line by a partition
+//     method computed on the fly: each lane eliminates a chunk of
+//     consecutive cells (Thomas with two spike columns), the chunk-end
+//     unknowns form a reduced tridiagonal system of one row per lane, solved
+//     by parallel cyclic reduction over wavefront shuffles (and, across the
+//     waves of a workgroup, through LDS), then the lane substitutes back;
+//   * fields that other workgroups read are written and read through
+//     device-coherent buffer accesses, so no workgroup has to write back
+//     its L2 at a barrier, and the grid-wide barrier has two levels (groups
+//     of workgroups, then the group leaders);
 //   * the largest change |T^{s+1} - T^s| of each line is folded into one
 //     device word per iteration by an atomic max (non-negative doubles order
 //     like their bit patterns); after a grid-wide barrier every wave reads the
