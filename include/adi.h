@@ -269,7 +269,8 @@ adi_status adi_set_step_rule(adi_problem p, double tau_trs_div, double tau_src_d
  * iterations stopped (the field and time then advance), else 0 (the field
  * is unchanged).  solves (nullable, 2): solves of each half step (-1: did
  * not stop, 0: not run).  changes (nullable, 2): the change norm that
- * decided each half.  Synchronises.  ADI_ESTATE before adi_set_laws. */
+ * decided each half.  Synchronises.  ADI_ESTATE before adi_set_laws;
+ * ADI_EDEVICE as for adi_nl_run. */
 adi_status adi_nl_step(adi_problem p, double tau, int32_t* accepted, int32_t solves[2], double changes[2]);
 
 typedef struct {
@@ -291,7 +292,11 @@ typedef struct {
  * log_cap accepted steps.  out (nullable) receives the report.
  * Synchronises.  ADI_EINVAL if halving went below tau_min (the field then
  * holds the last accepted step), ADI_EDEVICE if a grid-wide wait of the
- * kernel ran out. */
+ * kernel ran out (every wave leaves at its next wait; the problem's time
+ * is unchanged, its field undefined until adi_set_field).  A wait polls at
+ * most about 3e7 times (about a second); the environment variable
+ * ADI_NL_WAIT_POLLS, read at each call, sets another bound (0: abort at the
+ * first wait that would poll), so that callers can exercise this path. */
 adi_status adi_nl_run(adi_problem p, double t_end, int64_t max_steps, double* host_log, int64_t log_cap,
                       adi_nl_report* out);
 

@@ -4,6 +4,8 @@
 // of the persistent kernel of nonlinear.hpp and the reports.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -117,6 +119,10 @@ Args make_args(const ProblemCore& core, const State* s) {
   a.guard = 1e-9 * s->pulse.ttrs / s->div_trs;
   a.iter_max = s->iter_max;
   a.Mr = s->Mr; a.Gr = s->Gr; a.Mz = s->Mz; a.Gz = s->Gz; a.wz = s->wz;
+  // ADI_NL_WAIT_POLLS lowers the bound of every grid-wide wait, so that the
+  // abort path can be exercised from the host (every wave still exits).
+  const char* polls = getenv("ADI_NL_WAIT_POLLS");
+  a.spin_limit = polls ? std::max(0LL, atoll(polls)) : SPIN_LIMIT;
   return a;
 }
 

@@ -54,7 +54,7 @@ namespace nl {
 constexpr int ITER_CAP = 64;   // largest iteration limit per half step
 constexpr int MAX_M = 48;      // cells per lane: lines of up to 64 * 48 = 3072 cells
 constexpr int MIN_M = 3;       // a chunk has a first, an interior and a last cell
-constexpr long long SPIN_LIMIT = 1LL << 25;  // bounded grid-wide waits (about a second)
+constexpr long long SPIN_LIMIT = 1LL << 25;  // default bound of a grid-wide wait (about a second)
 constexpr unsigned BAR_GROUPS = 8;           // first level of the grid barrier
 constexpr int NW = 4;                        // waves per workgroup
 
@@ -121,6 +121,7 @@ struct Args {
   int attempts;     // attempts in this launch
   int Mr, Gr, Mz, Gz;   // chunking: r lines over NW waves, z lines over wz waves
   int wz;               // waves per z line: 1 or NW
+  long long spin_limit; // polls of a grid-wide wait before the run is aborted
 };
 
 // Device-scope accesses: coherent across XCDs without fences (see the
@@ -290,9 +291,9 @@ __device__ __forceinline__ void wave_sync() {
 // workgroups of each of 8 groups (by index) count on their group's word, the
 // last of a group counts on the top word, and the last group releases every
 // group's generation word, which its workgroups poll.  Returns false when
-// the run was aborted: some wave waited past the spin limit.  gen: this
+// the run was aborted: some wave polled more than `limit` times.  gen: this
 // workgroup's count of passed barriers.
-__device__ bool grid_sync(Ctl* c, unsigned nblocks, unsigned& gen) {
+__device__ bool grid_sync(Ctl* c, unsigned nblocks, unsigned& gen, long long limit) {
   __syncthreads();  // every wave's device-scope accesses have completed
   __shared__ int ok_s;
   if (threadIdx.x == 0) {
@@ -317,7 +318,7 @@ __device__ bool grid_sync(Ctl* c, unsigned nblocks, unsigned& gen) {
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > SPIN_LIMIT) {
+      if (++spins > limit) {
         ast(&c->abort, 1);
         ok = 0;
         break;
@@ -751,7 +752,7 @@ __global__ void __launch_bounds__(64 * NW) k_nl_run(Args a) {
       for (int j = blockIdx.x; j < a.P.nz; j += nb)
         lmax = nan_max(lmax, solve_line<0, NW>(a, laws, j, a.F[in], a.F[cur], a.E, a.F[o], s == 0, ta, pval, lds_all));
       if (threadIdx.x == 0 && !(lmax <= 0.0)) atomicMax(&c->chg[par][0][s], as_bits(lmax));
-      if (!grid_sync(c, nb, gen)) return;
+      if (!grid_sync(c, nb, gen, a.spin_limit)) return;
       chg_r = from_bits(ald(&c->chg[par][0][s]));
       in = o;
       if (chg_r < a.eps) {
@@ -780,7 +781,7 @@ __global__ void __launch_bounds__(64 * NW) k_nl_run(Args a) {
                                                    lds_all));
           if (threadIdx.x == 0 && !(lmax <= 0.0)) atomicMax(&c->chg[par][1][s], as_bits(lmax));
         }
-        if (!grid_sync(c, nb, gen)) return;
+        if (!grid_sync(c, nb, gen, a.spin_limit)) return;
         chg_z = from_bits(ald(&c->chg[par][1][s]));
         in = o;
         if (chg_z < a.eps) {
@@ -835,7 +836,7 @@ __global__ void __launch_bounds__(64 * NW) k_nl_run(Args a) {
       }
       publish(c, nt, ntau, ncur, nsteps, nrej, nends, status);
     }
-    if (!grid_sync(c, nb, gen)) return;
+    if (!grid_sync(c, nb, gen, a.spin_limit)) return;
     // periodic regime: at a period start, compare T with the field of the
     // previous period start
     if (ok && !a.single && ends_period && a.ptol > 0.0) {
@@ -849,7 +850,7 @@ __global__ void __launch_bounds__(64 * NW) k_nl_run(Args a) {
       }
       lmax = wave_max(lmax);
       if ((threadIdx.x & 63) == 0 && !(lmax <= 0.0)) atomicMax(&c->pchg, as_bits(lmax));
-      if (!grid_sync(c, nb, gen)) return;
+      if (!grid_sync(c, nb, gen, a.spin_limit)) return;
       if (lead) {
         const double d = from_bits(ald(&c->pchg));
         note_margin(c, d, a.ptol);
@@ -860,7 +861,7 @@ __global__ void __launch_bounds__(64 * NW) k_nl_run(Args a) {
         else begin_step(a, nt, nsteps, c->max_steps, c->t_end, ntau, nends, status);
         publish(c, nt, ntau, ald(&c->cur), nsteps, ald(&c->rejected), nends, status);
       }
-      if (!grid_sync(c, nb, gen)) return;
+      if (!grid_sync(c, nb, gen, a.spin_limit)) return;
     }
   }
 }

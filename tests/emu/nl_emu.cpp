@@ -101,6 +101,8 @@ int main(int argc, char** argv) {
   a.eps = ctl6[0]; a.iter_max = iter_max; a.tau_min = ctl6[1]; a.div_trs = ctl6[2]; a.div_src = ctl6[3];
   a.ptol = ctl6[4];
   a.guard = 1e-9 * pu.ttrs / a.div_trs;
+  const char* polls = getenv("ADI_NL_WAIT_POLLS");
+  a.spin_limit = polls ? std::max(0LL, atoll(polls)) : SPIN_LIMIT;
   chunk(nr, 64 * NW, a.Mr, a.Gr);
   chunk(nz, 64, a.Mz, a.Gz);
   a.wz = 1;

@@ -208,6 +208,32 @@ def test_case_study_scaled_grid_heating_pulse():
     assert err <= tol
 
 
+def test_wait_bound_aborts_and_problem_recovers(monkeypatch):
+    """The abort path of the kernel's grid-wide waits, forced from the host:
+    with ADI_NL_WAIT_POLLS=0 the first wait that would poll aborts the run,
+    every wave leaves at its next wait and adi_nl_run reports ADI_EDEVICE;
+    with the default bound the same problem, its field set again, then runs
+    to the oracle's result."""
+    from paper_1912_03744_amd import native
+    s = tiny_spec(10, 21)
+    laws = laws_of(s)
+    P = nl_problem(s, laws)
+    T0 = P.initial(0.2)
+    p = gpu_problem(s, laws, T0)
+    p.set_iteration(1e-10, 12)
+    monkeypatch.setenv("ADI_NL_WAIT_POLLS", "0")
+    with pytest.raises(native.AdiError) as e:
+        p.nl_run(2e-3)
+    assert e.value.status == native.ADI_EDEVICE
+    monkeypatch.delenv("ADI_NL_WAIT_POLLS")
+    p.set_field(T0)
+    want = P.nl_run(T0, 0.0, 2e-3, kind="const", eps=1e-10, iter_max=12)
+    assert want["min_margin"] > 1e-3
+    got = p.nl_run(2e-3)
+    assert got["steps"] == want["steps"] and got["solves_r"] == want["solves_r"]
+    assert rel_inf(p.read_field(), want["T"], P.active()) <= TOL
+
+
 def test_state_and_argument_errors():
     from paper_1912_03744_amd import native
     s = tiny_spec(7, 12)

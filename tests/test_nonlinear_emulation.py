@@ -71,9 +71,10 @@ def nl_problem(s, laws):
 
 def run_emu(emu, tmp_path, s, laws, T, *, grid, mode, kind="const", pulse=PULSE, eps=1e-10, iter_max=10,
             tau_min=1e-14, div_trs=1000.0, div_src=100.0, ptol=0.0, t0=0.0, t_end_or_tau=1e-3,
-            max_steps=1 << 40, log_cap=0, z_block=False):
+            max_steps=1 << 40, log_cap=0, z_block=False, polls=None):
     """z_block: solve the z lines with a whole workgroup each (the long-line
-    path) instead of one wave each."""
+    path) instead of one wave each; polls: bound of every grid-wide wait
+    (ADI_NL_WAIT_POLLS), None for the library's default."""
     inp, out = tmp_path / "in.txt", tmp_path / "out.txt"
     fmt = lambda v: " ".join("%.17g" % x for x in np.ravel(v))
     faces = s.r_faces is not None
@@ -88,6 +89,9 @@ def run_emu(emu, tmp_path, s, laws, T, *, grid, mode, kind="const", pulse=PULSE,
     env = dict(os.environ)
     if z_block:
         env["NL_EMU_WZ_BLOCK"] = "1"
+    env.pop("ADI_NL_WAIT_POLLS", None)
+    if polls is not None:
+        env["ADI_NL_WAIT_POLLS"] = str(polls)
     subprocess.run([str(emu), str(inp), str(out)], check=True, timeout=600, env=env)
     rows = out.read_text().split("\n")
     h = rows[0].split()
@@ -172,6 +176,25 @@ def test_adaptive_run_through_transitions(emu, tmp_path, kind):
     assert np.allclose(got["log"][:, :2], want["log"][:, :2], rtol=0, atol=1e-15)
     assert abs(got["t"] - want["t"]) <= 1e-15
     assert rel_inf(got["T"], want["T"], P.active()) <= TOL
+
+
+def test_wait_bound_aborts_the_run(emu, tmp_path):
+    """A grid-wide wait that runs out of polls aborts the run: the waiting
+    wave raises the abort flag, every other wave leaves at its next wait,
+    the kernel returns and the run reports the failed wait (status -2)
+    instead of hanging.  With one workgroup no wait ever polls, so the same
+    bound lets the run finish."""
+    s = tiny_spec(8, 15)
+    laws = laws_of(s)
+    P = nl_problem(s, laws)
+    T0 = P.initial(0.3)
+    kw = dict(kind="const", eps=1e-10, t_end_or_tau=0.01)
+    got = run_emu(emu, tmp_path, s, laws, T0, grid=4, mode=0, polls=0, **kw)
+    assert got["status"] == -2
+    one = run_emu(emu, tmp_path, s, laws, T0, grid=1, mode=0, polls=0, **kw)
+    want = P.nl_run(T0, 0.0, 0.01, kind="const", eps=1e-10)
+    assert one["status"] == 1 and one["steps"] == want["steps"]
+    assert rel_inf(one["T"], want["T"], P.active()) <= TOL
 
 
 def test_forced_halving_matches_oracle(emu, tmp_path):
