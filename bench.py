@@ -278,16 +278,20 @@ def single_layout_leg():
     return out
 
 
-MLP_FLOP_PER_SAMPLE = 2 * (12 * 256 + 3 * 256 * 256 + 256 * 64)   # 432,128: the forward pass's products
+def mlp_flop_per_sample(widths):
+    """Products of one forward pass: 2 * sum of n_in * n_out over the layers
+    (the first layer's 12 inputs, not its padding)."""
+    return 2 * sum(a * b for a, b in zip(widths[:-1], widths[1:]))
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def surrogate_leg(batch=65536, reps=50):
-    """Surrogate inference on the matrix cores: the 12 -> 4 x 256 GELU -> 64
-    network (bf16 operands, fp32 accumulation and output) over a batch of
-    `batch` seeded feature rows, `reps` forward passes timed with HIP events
-    on the network's stream; throughput in samples/s and the products'
-    rate against the dense bf16 MFMA peak (432,128 flops per sample)."""
+    """Surrogate inference on the matrix cores: the surrogate's network (12
+    -> 4 x 256 GELU -> 128; bf16 operands, fp32 accumulation and output) over
+    a batch of `batch` seeded feature rows, `reps` forward passes timed with
+    HIP events on the network's stream; throughput in samples/s and the
+    products' rate against the dense bf16 MFMA peak (464,896 flops per
+    sample)."""
     import numpy as np
     import torch
 
@@ -302,7 +306,7 @@ def surrogate_leg(batch=65536, reps=50):
         lo = np.concatenate([S.BOX_LO, [S.LOGT_LO]])
         hi = np.concatenate([S.BOX_HI, [S.LOGT_HI]])
         x = torch.tensor(rng.uniform(lo, hi, size=(batch, 12)).astype(np.float32), device="cuda")
-        y = torch.empty(batch, 64, device="cuda")
+        y = torch.empty(batch, S.WIDTHS[-1], device="cuda")
         for _ in range(3):
             net.forward(x, y)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -312,10 +316,10 @@ def surrogate_leg(batch=65536, reps=50):
         ev1.record(stream)
         ev1.synchronize()
         ms = ev0.elapsed_time(ev1) / reps
-    tflops = MLP_FLOP_PER_SAMPLE * batch / (ms * 1e-3) / 1e12
+    tflops = mlp_flop_per_sample(S.WIDTHS) * batch / (ms * 1e-3) / 1e12
     net.close()
-    return {"workload": "surrogate forward pass, 12 -> 4 x 256 (GELU) -> 64, bf16 matrix cores with fp32 "
-                        "accumulation, batch %d, seeded inputs over the design box" % batch,
+    return {"workload": "surrogate forward pass, 12 -> 4 x 256 (GELU) -> %d, bf16 matrix cores with fp32 "
+                        "accumulation, batch %d, seeded inputs over the design box" % (S.WIDTHS[-1], batch),
             "value": batch / (ms * 1e-3), "unit": "samples/s", "ms_per_batch": ms,
             "roofline": {"bound": "mfma", "kernel": "k_layer (all layers)", "achieved": tflops,
                          "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,

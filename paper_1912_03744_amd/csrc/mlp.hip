@@ -584,6 +584,7 @@ adi_status layer_forward(adi_mlp m, int l, int epi, const __bf16* in, long B, fl
   if (kd == 64 && nd == 256) return launch_layer<64, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
   if (kd == 256 && nd == 256) return launch_layer<256, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
   if (kd == 256 && nd == 64) return launch_layer<256, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (kd == 256 && nd == 128) return launch_layer<256, 128>(m, epi, in, m->Wtb[l], bias, B, of, ob);
   if (kd == 64 && nd == 64) return launch_layer<64, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
   GemmArgs g{};
   g.A = in;

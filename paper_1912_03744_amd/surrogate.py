@@ -9,21 +9,26 @@ tensors as device memory), schedules and bookkeeping.
 Inputs (12 features): log10 k of the five regions, heater source Q,
 log10 h, r0, r1, r2, z0 and time t; each mapped affinely to [-1, 1] over the
 design box on the device (time enters as log10 t: heat reaches the terminal
-on a diffusion time scale, so log k and log t combine additively).  Output:
-64 values z_k = ln(y_k + Y_FLOOR) of the scaled outer terminal-face profile
-y_k = T_k / (Q t) (top row resampled at r_k = (k+0.5) rmax/64), decoded as
-exp(z) - Y_FLOOR.  rho c = 1, so y is in [0, 1] by the maximum principle
-(Q >= 0, T0 = T_inf = 0); the logarithm makes the squared loss a
-relative-error loss across the many decades the terminal temperature spans,
-and the floor maps a terminal that has not yet warmed to ~0.
-Relative errors are measured against max(max_k |T_k|, Y_FLOOR Q t), since
-early on the terminal face has not yet warmed and its temperature is ~0.
+on a diffusion time scale, so log k and log t combine additively).
+Target: the scaled outer terminal-face profile y_k = T_k / (Q t) (top row
+resampled at r_k = (k+0.5) rmax/64; rho c = 1, so y is in [0, 1] by the
+maximum principle for Q >= 0, T0 = T_inf = 0) split into its scale and its
+shape: outputs 0..63 are the shape u_k = y_k / max_k y, outputs 64..127 all
+the log scale ln(max_k y), standardised over the training labels; the
+prediction is exp(mean of outputs 64..127) * u_k.  Both parts are O(1), so
+the network's bf16 hidden activations resolve them to a small fraction of
+their range; a per-point logarithm ln(y_k + 1e-6), tried first, left every
+design with about 3 % error (65,536 label designs) and could not represent a
+terminal that has not warmed.  Relative errors are measured against
+max(max_k |T_k|, Y_FLOOR Q t), since early on the terminal face has not
+yet warmed and its temperature is ~0.
 
 Gate (when the surrogate's answer is kept): the design lies in the training
 box, every predicted y_k lies in [0, 1], and the two ensemble members
-disagree by at most delta (max_k |y1 - y2| / max_k |ybar|), with delta
-calibrated on validation solves so that accepted designs stayed within the
-target relative error.  Rejected designs are re-solved by the FP64 solver.
+disagree by at most delta (max_k |y1 - y2| / max(max_k |ybar|, Y_FLOOR)),
+with delta calibrated on validation solves so that accepted designs stayed
+within half the target relative error (a margin for designs the validation
+set did not see).  Rejected designs are re-solved by the FP64 solver.
 """
 from __future__ import annotations
 
@@ -40,7 +45,7 @@ from . import workloads as W
 BOX_LO = np.array([-2, -2, -2, -2, -2, 0.5, -2, 1.5, 2.0, 2.5, 6.0], dtype=np.float64)
 BOX_HI = np.array([1, 1, 1, 1, 1, 2.0, 0, 2.5, 4.0, 5.5, 9.0], dtype=np.float64)
 LOGT_LO, LOGT_HI = -1.0, math.log10(2.0)
-WIDTHS = [12, 256, 256, 256, 256, 64]
+WIDTHS = [12, 256, 256, 256, 256, 128]
 LABEL_GRID = (128, 320)
 NPTS = 64
 Y_FLOOR = 1e-6
@@ -105,7 +110,8 @@ def solve_profiles(D: np.ndarray, nsteps=2000, dt=1e-3, snap_every=100, grid=LAB
 
 def make_pairs(D: np.ndarray, prof: np.ndarray, snap_dt: float):
     """(X, Y): one row per (design, snapshot); Y = scaled profile
-    y = T / (Q t) (float64, for judging); the network target is encode(Y)."""
+    y = T / (Q t) (float64, for judging); the network target is
+    encode(Y, *fit_scale(Y_train))."""
     n, nsnap, _ = prof.shape
     t = snap_dt * (np.arange(nsnap) + 1)
     X = features(np.repeat(D, nsnap, axis=0), np.tile(t, n))
@@ -114,12 +120,34 @@ def make_pairs(D: np.ndarray, prof: np.ndarray, snap_dt: float):
     return X, Y
 
 
-def encode(y):
-    return np.log(np.maximum(y, 0.0) + Y_FLOOR).astype(np.float32)
+SCALE_MIN = 1e-30  # profiles whose maximum is below this count as exactly cold
 
 
-def decode(z):
-    return np.exp(z.astype(np.float64)) - Y_FLOOR
+def log_scale(y):
+    return np.log(np.maximum(np.max(y, axis=-1), SCALE_MIN))
+
+
+def fit_scale(Y):
+    """Mean and standard deviation of the log scale over training labels."""
+    s = log_scale(Y)
+    return float(s.mean()), float(max(s.std(), 1e-12))
+
+
+def encode(y, mu, sd):
+    """Network targets [n, 128] of scaled profiles y [n, 64]: the shape
+    y / max y, then the standardised log scale in every one of the other 64
+    outputs."""
+    y = np.maximum(np.asarray(y, dtype=np.float64), 0.0)
+    m = np.maximum(np.max(y, axis=-1), SCALE_MIN)
+    z = (np.log(m) - mu) / sd
+    return np.concatenate([y / m[..., None], np.repeat(z[..., None], NPTS, axis=-1)], axis=-1).astype(np.float32)
+
+
+def decode(P, mu, sd):
+    """Scaled profiles [..., 64] from network outputs [..., 128]."""
+    P = np.asarray(P, dtype=np.float64)
+    scale = np.exp(P[..., NPTS:].mean(axis=-1) * sd + mu)
+    return scale[..., None] * P[..., :NPTS]
 
 
 @dataclass
@@ -127,37 +155,38 @@ class Surrogate:
     nets: list
     delta: float = math.inf
     history: list = field(default_factory=list)
+    mu: float = 0.0   # log-scale standardisation of the targets
+    sd: float = 1.0
 
     def predict(self, X: np.ndarray, chunk=65536):
         """Ensemble predictions [members, n, 64] (numpy) for feature rows X."""
         import torch
         n = len(X)
-        out = np.empty((len(self.nets), n, NPTS), dtype=np.float32)
+        nout = WIDTHS[-1]
+        out = np.empty((len(self.nets), n, nout), dtype=np.float32)
         for a in range(0, n, chunk):
             xb = X[a:a + chunk]
             m = len(xb)
             pad = (-m) % 64
             xt = torch.zeros(m + pad, X.shape[1], device="cuda")
             xt[:m] = torch.from_numpy(np.ascontiguousarray(xb, dtype=np.float32)).cuda()
-            yt = torch.empty(m + pad, NPTS, device="cuda")
+            yt = torch.empty(m + pad, nout, device="cuda")
             for i, net in enumerate(self.nets):
                 net.forward(xt, yt)
                 torch.cuda.synchronize()
                 out[i, a:a + m] = yt[:m].cpu().numpy()
         return out
 
-    @staticmethod
-    def disagreement(P: np.ndarray) -> np.ndarray:
+    def disagreement(self, P: np.ndarray) -> np.ndarray:
         """Relative disagreement of the first and last members on the
-        scaled profile (network outputs are logarithms)."""
-        y0, y1 = decode(P[0]), decode(P[-1])
+        scaled profile."""
+        y0, y1 = decode(P[0], self.mu, self.sd), decode(P[-1], self.mu, self.sd)
         ybar = 0.5 * (y0 + y1)
         return np.max(np.abs(y0 - y1), axis=1) / np.maximum(np.max(ybar, axis=1), Y_FLOOR)
 
-    @staticmethod
-    def profile(P: np.ndarray) -> np.ndarray:
+    def profile(self, P: np.ndarray) -> np.ndarray:
         """Ensemble-mean scaled profile y."""
-        return decode(P).mean(axis=0)
+        return decode(P, self.mu, self.sd).mean(axis=0)
 
     def gate(self, D: np.ndarray, P: np.ndarray) -> np.ndarray:
         """True where the surrogate's answer is kept."""
@@ -179,8 +208,9 @@ def train(X: np.ndarray, Y: np.ndarray, members=2, epochs=30, batch=4096, lr=2e-
     """Train an ensemble (different initialisations and data orders)."""
     import torch
     shift, scale = feature_scaling()
+    mu, sd = fit_scale(Y)
     xt = torch.from_numpy(np.ascontiguousarray(X)).cuda()
-    yt = torch.from_numpy(np.ascontiguousarray(encode(Y))).cuda()
+    yt = torch.from_numpy(np.ascontiguousarray(encode(Y, mu, sd))).cuda()
     n = (len(X) // batch) * batch
     nets, hist = [], []
     steps = epochs * (n // batch)
@@ -208,25 +238,27 @@ def train(X: np.ndarray, Y: np.ndarray, members=2, epochs=30, batch=4096, lr=2e-
             if log and (ep % 5 == 4 or ep == epochs - 1):
                 log("member %d epoch %d loss %.3e (%.1f s)" % (mi, ep + 1, last, time.perf_counter() - t0))
         nets.append(net)
-    return Surrogate(nets=nets, history=hist)
+    return Surrogate(nets=nets, history=hist, mu=mu, sd=sd)
 
 
-def calibrate(sur: Surrogate, Xv: np.ndarray, Yv: np.ndarray, target=1e-3, also=(1e-2,)):
+def calibrate(sur: Surrogate, Xv: np.ndarray, Yv: np.ndarray, target=1e-3, also=(1e-2,), margin=0.5):
     """Largest ensemble-disagreement threshold such that every validation
-    pair accepted under it has relative profile error <= target (set as the
-    gate); the thresholds for the `also` targets are reported beside it."""
+    pair accepted under it has relative profile error <= margin * target
+    (set as the gate); the thresholds for the `also` targets are reported
+    beside it."""
     P = sur.predict(Xv)
-    err = rel_profile_error(Surrogate.profile(P), Yv)
-    dis = Surrogate.disagreement(P)
+    err = rel_profile_error(sur.profile(P), Yv)
+    dis = sur.disagreement(P)
     order = np.argsort(dis)
 
     def thresh(tg):
-        bad = np.nonzero(err[order] > tg)[0]
+        bad = np.nonzero(err[order] > margin * tg)[0]
         k = int(bad[0]) if len(bad) else len(order)
         return (float(dis[order[k - 1]]) if k > 0 else 0.0), k / len(order)
 
     sur.delta, rate = thresh(target)
-    out = {"target": target, "delta": sur.delta, "val_accept_rate": rate, "val_median_err": float(np.median(err)),
+    out = {"target": target, "margin": margin, "delta": sur.delta, "val_accept_rate": rate,
+           "val_median_err": float(np.median(err)),
            "val_p99_err": float(np.quantile(err, 0.99)), "val_max_err": float(err.max())}
     for tg in also:
         d, r = thresh(tg)
@@ -294,7 +326,7 @@ def _run(n_train, n_val, n_test, n_sweep, top_frac, epochs, n_recall, n_plain, l
     log("calibration %s" % res["calibration"])
     # held-out judgement, every snapshot time
     P = sur.predict(Xte)
-    err = rel_profile_error(Surrogate.profile(P), Yte)
+    err = rel_profile_error(sur.profile(P), Yte)
     ok = sur.gate(Xte[:, :11].astype(np.float64), P)
     d_main = sur.delta
     sur.delta = res["calibration"]["delta_at_0.01"]
@@ -308,6 +340,9 @@ def _run(n_train, n_val, n_test, n_sweep, top_frac, epochs, n_recall, n_plain, l
                       "frac_err_le_1e-3": float(np.mean(err <= 1e-3)),
                       "frac_err_le_1e-2": float(np.mean(err <= 1e-2)),
                       "median_err_at_t2": float(np.median(err.reshape(-1, 20)[:, -1])),
+                      "median_err_by_time": [float(x) for x in np.median(err.reshape(-1, 20), axis=0)],
+                      "gate_pass_rate_by_time": [float(x) for x in ok.reshape(-1, 20).mean(axis=0)],
+                      "frac_err_le_1e-3_at_t2": float(np.mean(err.reshape(-1, 20)[:, -1] <= 1e-3)),
                       "gate_pass_rate_at_1e-2": float(ok2.mean()),
                       "max_err_passed_at_1e-2": float(err[ok2].max()) if ok2.any() else None}
     log("held-out %s" % res["heldout"])
@@ -322,7 +357,7 @@ def _run(n_train, n_val, n_test, n_sweep, top_frac, epochs, n_recall, n_plain, l
     Psw = sur.predict(Xsw)
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
-    ybar = Surrogate.profile(Psw)
+    ybar = sur.profile(Psw)
     peak_pred = ybar.max(axis=1) * Dsw[:, 5] * 2.0
     gate_ok = sur.gate(Dsw, Psw)
     k = int(round(top_frac * n_sweep))

@@ -49,7 +49,8 @@ def _setup(widths, seed, B):
     return net, xd, td, ps, xe, t, p
 
 
-@pytest.mark.parametrize("widths", [[12, 64, 64], WIDTHS], ids=["small", "surrogate"])
+@pytest.mark.parametrize("widths", [[12, 64, 64], WIDTHS, [12, 256, 256, 256, 256, 128]],
+                         ids=["small", "surrogate64", "surrogate128"])
 def test_forward_matches_oracle(widths):
     import torch
     net, xd, td, ps, xe, t, _ = _setup(widths, 1, 512)

@@ -4,13 +4,15 @@ held-out judgement and the screened sweep against the plain and batched
 solvers.
 
 Checks, beyond the bookkeeping:
+  * the gate calibrated for the 1e-3 target keeps some of the held-out
+    (design, time) pairs, and every kept one is within 1e-3 of the solver;
   * the designs the screened sweep re-solves come back with the FP64
     solver's values: three of the selected designs are solved again by the
     oracle (5000 steps of 4e-4 on 128 x 320) and their terminal-face
     profiles agree with the pipeline's to 1e-12;
   * the network ranks: its top 1 % of a fully solved subset recovers at
     40 % of the true top 1 % (random selection recovers 1 % on
-    average; the trained network at full scale recovers 98 %), and its peak
+    average; the trained network at full scale recovers 97 %), and its peak
     predictions correlate with the solver's (Spearman >= 0.9 on the subset);
   * the screened sweep evaluates designs faster than the plain per-instance
     solver."""
@@ -30,11 +32,11 @@ def test_screened_sweep_small():
                 log=lambda m: print(m, flush=True))
     h, sw, sel = res["heldout"], res["sweep"], res["_selected"]
     print({k: v for k, v in res.items() if not k.startswith("_")}, flush=True)
-    assert 0.0 <= h["gate_pass_rate"] <= 1.0
-    # the calibrated gate never keeps a validation design above the target
+    # the calibrated gate keeps a share of the held-out designs, all of them
+    # within the 1e-3 target
     assert res["calibration"]["delta"] >= 0.0
-    if h["max_err_passed"] is not None:
-        assert np.isfinite(h["max_err_passed"])
+    assert h["gate_pass_rate"] > 0.05, h["gate_pass_rate"]
+    assert h["max_err_passed"] is not None and h["max_err_passed"] <= 1e-3, h["max_err_passed"]
     assert sw["selected"] == 164 and len(sel["designs"]) == 164
     # ranking quality on the fully solved subset
     assert sw["recall_at_top"] >= 0.4, sw["recall_at_top"]
