@@ -439,6 +439,29 @@ adi_status adi_mlp_forward_noalloc(adi_mlp m, const float* dev_x, int64_t batch,
 
 void adi_mlp_destroy(adi_mlp m);
 
+/* Screening reductions of the surrogate's design sweep, on the device.
+ * dev_pred: [members][n][nout] fp32 network outputs, for each design the
+ * shape of its scaled terminal-face profile (outputs 0..63) and its
+ * standardised log scale (outputs 64..nout-1, averaged): member m's profile
+ * is y_k = exp(mu + sd * scale) * shape_k, the ensemble's ybar_k the mean
+ * over the members.  Per design: dev_peak = max_k ybar_k * qt (dev_qt:
+ * n values, e.g. Q t to turn y into a temperature; NULL: 1), dev_dis = the
+ * disagreement max_k |y_first - y_last| / max(max_k ybar_k, floor_),
+ * dev_bound_ok = 1 if every ybar_k <= 1 + 1e-3 (the maximum principle of
+ * the scaled profile).  64 < nout <= 4096.  Asynchronous on hip_stream. */
+adi_status adi_screen_profiles(const float* dev_pred, int32_t members, int64_t n, int32_t nout, double mu,
+                               double sd, double floor_, const double* dev_qt, double* dev_peak, double* dev_dis,
+                               uint8_t* dev_bound_ok, void* hip_stream);
+
+/* Indices of the k largest of n device doubles (1 <= k <= n; NaN below
+ * every number; of equal values the lower indices first), into dev_idx (k
+ * int64): first those above the k-th largest value in ascending index
+ * order, then those equal to it, in ascending index order.  Radix
+ * selection on the device (eight 8-bit passes) and an order-keeping
+ * compaction; work buffers from the library's allocator.  Synchronises
+ * hip_stream. */
+adi_status adi_top_k(const double* dev_vals, int64_t n, int32_t k, int64_t* dev_idx, void* hip_stream);
+
 /* ---------------------------------------------------------- utilities -- */
 
 /* Device-memory hook (for a caller's caching allocator, e.g. PyTorch's):

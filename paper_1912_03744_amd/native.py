@@ -127,6 +127,9 @@ _SIGS = {
     "adi_mlp_gradients": [_vp, _vp, _vp, ctypes.c_int64, _fp, _fp],
     "adi_mlp_train_step": [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, _fp],
     "adi_mlp_destroy": [_vp],
+    "adi_screen_profiles": [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, _vp, _vp, _vp, _vp, _vp],
+    "adi_top_k": [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp],
     "adi_status_string": [ctypes.c_int],
     "adi_last_error": [],
     "adi_version": [],
@@ -566,6 +569,47 @@ class MLP:
                                        int(x.shape[0]), float(lr), ctypes.byref(loss) if want_loss else None))
         self._after()
         return loss.value if want_loss else None
+
+
+def _stream_handle(stream):
+    import torch
+    return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def screen_profiles(pred, mu, sd, floor, qt=None, stream=None):
+    """adi_screen_profiles on a contiguous float32 device tensor pred
+    [members, n, nout]: returns device tensors (peak float64 [n],
+    disagreement float64 [n], bound_ok uint8 [n]); qt: float64 device
+    tensor [n] or None.  Asynchronous on `stream` (default: torch's current
+    stream)."""
+    import torch
+    if pred.dtype != torch.float32 or not pred.is_contiguous() or pred.dim() != 3:
+        raise ValueError("pred must be a contiguous float32 tensor [members, n, nout]")
+    members, n, nout = pred.shape
+    dev = pred.device
+    peak = torch.empty(n, dtype=torch.float64, device=dev)
+    dis = torch.empty(n, dtype=torch.float64, device=dev)
+    ok = torch.empty(n, dtype=torch.uint8, device=dev)
+    if qt is not None and (qt.dtype != torch.float64 or not qt.is_contiguous() or qt.numel() != n):
+        raise ValueError("qt must be a contiguous float64 tensor of n values")
+    check(lib().adi_screen_profiles(ctypes.c_void_p(pred.data_ptr()), int(members), int(n), int(nout), float(mu),
+                                    float(sd), float(floor), ctypes.c_void_p(qt.data_ptr()) if qt is not None else None,
+                                    ctypes.c_void_p(peak.data_ptr()), ctypes.c_void_p(dis.data_ptr()),
+                                    ctypes.c_void_p(ok.data_ptr()), _stream_handle(stream)))
+    return peak, dis, ok
+
+
+def top_k(vals, k, stream=None):
+    """adi_top_k on a contiguous float64 device tensor: int64 device tensor
+    of the k largest values' indices (those above the k-th largest first,
+    then its ties, each in ascending index order).  Synchronises."""
+    import torch
+    if vals.dtype != torch.float64 or not vals.is_contiguous():
+        raise ValueError("vals must be a contiguous float64 tensor")
+    idx = torch.empty(max(int(k), 1), dtype=torch.int64, device=vals.device)
+    check(lib().adi_top_k(ctypes.c_void_p(vals.data_ptr()), int(vals.numel()), int(k),
+                          ctypes.c_void_p(idx.data_ptr()), _stream_handle(stream)))
+    return idx[:int(k)]
 
 
 def launch_shapes():
