@@ -153,10 +153,11 @@ def batch_leg(n, steps, tune=True, shape=(2, 8, 1)):
     if tune:
         t0 = time.perf_counter()
         tuned = autotune.apply_batch(b, dt, "pr")
-        shape = tuple(tuned["shape"])
-        print("bench: batch autotune %.1f s -> %s" % (time.perf_counter() - t0, tuned["shape"]),
-              file=sys.stderr, flush=True)
+        shape, zshape = tuple(tuned["shape"]), list(tuned["zshape"])
+        print("bench: batch autotune %.1f s -> %s, z shapes %s" % (time.perf_counter() - t0, tuned["shape"],
+                                                                    zshape), file=sys.stderr, flush=True)
     else:
+        zshape = [0, 0, 0, 0]
         b.set_launch(*shape)
     mode = ("batched sweep launches (one per half step and line shape), captured 256 steps per graph"
             if shape[1] == 1 else "one persistent launch")
@@ -171,6 +172,8 @@ def batch_leg(n, steps, tune=True, shape=(2, 8, 1)):
            "value": active * steps / sec, "unit": "cell-updates/s", "cups_all_cells": cells * steps / sec,
            "seconds": sec, "designs_per_s": n / sec, "active_cells": active, "cells": cells,
            "launch": list(shape), "workgroups": info["workgroups"],
+           "zshape": {"variant_per_class": zshape,
+                      "shapes": [list(native.batch_zshapes()[c]["shapes"][v]) for c, v in enumerate(zshape)]},
            "roofline": {"bound": "hbm", "kernel": "batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
     b.close()

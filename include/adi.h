@@ -332,6 +332,23 @@ adi_status adi_batch_set_initial(adi_batch b, const double* T0);
 adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t waves_per_block,
                                 int32_t blocks_per_cu);
 
+/* Compiled shapes of the z lines in the batched sweep launches, by z class:
+ * the instances whose columns have up to 192, 256, 320 or 512 rows are
+ * classes 0..3 (one z launch per class and half step).  Shape `variant` of
+ * a class puts each block of 4 columns on a workgroup of *waves waves of 64
+ * chunks of *cells cells (the line solve of Sec. 3-4 split by the partition
+ * method); *max_rows receives the class's longest column.  Variant 0 is the
+ * default.  Needs no device.  ADI_EINVAL for a class or variant out of range
+ * (the outputs are then left unchanged). */
+adi_status adi_batch_zshape_info(int32_t zclass, int32_t variant, int32_t* waves, int32_t* cells,
+                                 int32_t* max_rows);
+
+/* Use shape `variant` (see adi_batch_zshape_info) for the z lines of class
+ * zclass in the batched sweep launches, from the next adi_batch_step on
+ * (the autotuner picks one per class).  Results do not depend on the shape
+ * beyond rounding.  ADI_EINVAL for a class or variant out of range. */
+adi_status adi_batch_set_zshape(adi_batch b, int32_t zclass, int32_t variant);
+
 /* Advance every instance nsteps steps of size dt from its initial field
  * (each call starts again from the initial fields), recording the outer
  * terminal-face profile (top row resampled at r_k = (k+0.5)*rmax/npts, as in

@@ -171,11 +171,28 @@ def batch_key(batch, scheme):
                                   scheme)
 
 
+def z_class(nz, classes):
+    """z class of the batched sweep launches for columns of nz rows."""
+    for c, cl in enumerate(classes):
+        if nz <= cl["max_rows"]:
+            return c
+    raise ValueError("no z class holds %d rows" % nz)
+
+
 def tune_batch(batch, dt, nsteps=100, verbose=False, log=None):
     """Time every batch launch shape on nsteps steps of the batch itself and
-    set the fastest.  Returns {"shape": (R, waves, blocks_per_cu), "ms": t,
-    "trials": [...]}."""
+    set the fastest; when that is the batched sweep launches, then time each
+    z shape of each size class present (the other classes at their best so
+    far) and keep the fastest per class.  Returns {"shape": (R, waves,
+    blocks_per_cu), "zshape": [variant per z class], "ms": t, "trials":
+    [...]}."""
+    def say(msg):
+        if verbose:
+            print(msg, flush=True) if log is None else log(msg)
+
     trials, best = [], None
+    for c in range(4):
+        batch.set_zshape(c, 0)
     for r, nw in BATCH_KERNELS:
         # one wave per workgroup: batched sweep launches, no persistent workgroups
         for bpc in (BATCH_BLOCKS_PER_CU if nw > 1 else (1,)):
@@ -183,26 +200,43 @@ def tune_batch(batch, dt, nsteps=100, verbose=False, log=None):
             batch.time(dt, nsteps, 1)  # first call allocates the workgroup scratch
             t = batch.time(dt, nsteps, 1)
             trials.append({"shape": (r, nw, bpc), "ms": t})
-            if verbose:
-                msg = "autotune batch shape %s: %.3f ms for %d steps" % ((r, nw, bpc), t, nsteps)
-                print(msg, flush=True) if log is None else log(msg)
+            say("autotune batch shape %s: %.3f ms for %d steps" % ((r, nw, bpc), t, nsteps))
             if best is None or t < best[1]:
                 best = ((r, nw, bpc), t)
     batch.set_launch(*best[0])
-    return {"shape": best[0], "ms": best[1], "trials": trials}
+    zshape = [0, 0, 0, 0]
+    if best[0][1] == 1:
+        from . import native
+        classes = native.batch_zshapes()
+        t_best = best[1]
+        for c in sorted({z_class(nz, classes) for _, nz in batch.shapes}):
+            for v in range(1, len(classes[c]["shapes"])):
+                batch.set_zshape(c, v)
+                t = batch.time(dt, nsteps, 1)
+                trials.append({"shape": best[0], "zshape": (c, v), "ms": t})
+                say("autotune batch z class %d shape %s: %.3f ms for %d steps"
+                    % (c, classes[c]["shapes"][v], t, nsteps))
+                if t < t_best:
+                    t_best, zshape[c] = t, v
+            batch.set_zshape(c, zshape[c])
+        best = (best[0], t_best)
+    return {"shape": best[0], "zshape": zshape, "ms": best[1], "trials": trials}
 
 
 def apply_batch(batch, dt, scheme, nsteps=100, retune=False, verbose=False, log=None):
-    """Set the cached best batch shape for this size mix, tuning on a miss."""
+    """Set the cached best batch shape (and z shape per size class) for this
+    size mix, tuning on a miss."""
     db = _load()
     k = batch_key(batch, scheme)
-    if not retune and k in db:
+    if not retune and k in db and "zshape" in db[k]:
         batch.set_launch(*db[k]["shape"])
+        for c, v in enumerate(db[k]["zshape"]):
+            batch.set_zshape(c, v)
         return db[k]
     t0 = time.time()
     r = tune_batch(batch, dt, nsteps, verbose=verbose, log=log)
-    entry = {"shape": list(r["shape"]), "ms": r["ms"], "steps": nsteps, "seconds": time.time() - t0,
-             "trials": len(r["trials"])}
+    entry = {"shape": list(r["shape"]), "zshape": list(r["zshape"]), "ms": r["ms"], "steps": nsteps,
+             "seconds": time.time() - t0, "trials": len(r["trials"])}
     db = _load()
     db[k] = entry
     _store(db)

@@ -255,6 +255,7 @@ struct adi_batch_s {
   int* smap = nullptr;
   int nmap_r[3] = {0, 0, 0}, rmap_off[3] = {0, 0, 0};  // r: slots of 16, 32, 64 tiles
   int nmap_z[4] = {0, 0, 0, 0}, zmap_off[4] = {0, 0, 0, 0};
+  int zvar[4] = {0, 0, 0, 0};  // candidate shape of each z class
 };
 
 namespace {
@@ -320,6 +321,7 @@ void launch_sweeps(adi_batch b, int64_t st0, int64_t st1, int64_t nsteps, int sn
   a.prof = b->prof_out;
   a.npts = npts;
   a.map = b->smap;
+  for (int c = 0; c < 4; ++c) a.zvar[c] = b->zvar[c];
   if (st0 == 1) hipLaunchKernelGGL(k_bsetup, dim3(b->n), dim3(256), 0, b->stream, a);
   for (int64_t st = st0; st <= st1; ++st) {
     const int64_t snap = snapshot_every > 0 ? st / snapshot_every - 1 : -1;  // index if st is a snapshot step
@@ -335,13 +337,10 @@ void launch_sweeps(adi_batch b, int64_t st0, int64_t st1, int64_t nsteps, int sn
     for (int c = 0; c < 4; ++c) {
       if (!b->nmap_z[c]) continue;
       a.map = b->smap + b->zmap_off[c];
-      constexpr int W3 = kBWZ_G[3] / 64;
-      switch (c) {
-        case 0: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[0], 1>), dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
-        case 1: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[1], 1>), dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
-        case 2: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[2], 1>), dim3(b->nmap_z[c]), dim3(64), 0, b->stream, a, write_T); break;
-        default: hipLaunchKernelGGL((k_bsweep_z<kBWZ_M[3], W3>), dim3(b->nmap_z[c]), dim3(64 * W3), 0, b->stream, a, write_T); break;
-      }
+      bwz_dispatch(c, b->zvar[c], [&](auto m, auto nw) {
+        constexpr int M = decltype(m)::value, NW = decltype(nw)::value;
+        hipLaunchKernelGGL((k_bsweep_z<M, NW>), dim3(b->nmap_z[c]), dim3(64 * NW), 0, b->stream, a, write_T);
+      });
     }
     if (take) hipLaunchKernelGGL(k_bprofile, dim3(b->n), dim3(64), 0, b->stream, a, (int)snap, nsnap);
   }
@@ -502,6 +501,25 @@ adi_status adi_batch_set_launch(adi_batch b, int32_t lines_per_lane, int32_t wav
   if (blocks_per_cu < 1 || blocks_per_cu > 8) return fail(ADI_EINVAL, "blocks_per_cu must be in [1, 8]");
   b->variant = v;
   b->blocks_per_cu = blocks_per_cu;
+  return ADI_OK;
+}
+
+adi_status adi_batch_zshape_info(int32_t zclass, int32_t variant, int32_t* waves, int32_t* cells,
+                                 int32_t* max_rows) {
+  if (!waves || !cells || !max_rows) return fail(ADI_EINVAL, "null output");
+  if (zclass < 0 || zclass > 3) return fail(ADI_EINVAL, "z class %d outside 0..3", zclass);
+  if (!bwz_valid(zclass, variant)) return fail(ADI_EINVAL, "z class %d has no shape %d", zclass, variant);
+  *waves = kBWZ_W[zclass][variant];
+  *cells = kBWZ_CM[zclass][variant];
+  *max_rows = kBS_G * kBSZ_M[zclass];
+  return ADI_OK;
+}
+
+adi_status adi_batch_set_zshape(adi_batch b, int32_t zclass, int32_t variant) {
+  ADI_TRY(batch_handle(b));
+  if (zclass < 0 || zclass > 3) return fail(ADI_EINVAL, "z class %d outside 0..3", zclass);
+  if (!bwz_valid(zclass, variant)) return fail(ADI_EINVAL, "z class %d has no shape %d", zclass, variant);
+  b->zvar[zclass] = variant;
   return ADI_OK;
 }
 

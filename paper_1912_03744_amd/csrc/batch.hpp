@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "device.hpp"
@@ -66,10 +67,36 @@ __device__ __forceinline__ void skip_range(int dir, int cls, const int* ranges, 
 constexpr int kBSR_M = 4;
 constexpr int kBSZ_M[4] = {3, 4, 5, 8};
 constexpr int kBS_G = 64;
-// z lines of the batched sweep launches: chunks (64 per wave) and cells per
-// chunk of each z shape (the longest lines on two waves of 4-cell chunks)
-constexpr int kBWZ_G[4] = {64, 64, 64, 128};
-constexpr int kBWZ_M[4] = {3, 4, 5, 4};
+// z lines of the batched sweep launches: candidate shapes of each z shape
+// class (lines up to 192, 256, 320, 512 rows), as waves of 64 chunks and
+// cells per chunk; every candidate covers its class's longest lines, the
+// first is the default and the autotuner picks one per class (0 = unused).
+constexpr int kBWZ_NV = 3;
+constexpr int kBWZ_W[4][kBWZ_NV] = {{1, 2, 0}, {1, 2, 0}, {1, 2, 0}, {2, 1, 3}};
+constexpr int kBWZ_CM[4][kBWZ_NV] = {{3, 3, 0}, {4, 3, 0}, {5, 3, 0}, {4, 8, 3}};
+
+__host__ __device__ constexpr bool bwz_valid(int c, int v) {
+  return c >= 0 && c < 4 && v >= 0 && v < kBWZ_NV && kBWZ_W[c][v] > 0;
+}
+
+// Calls f(integral_constant<M>, integral_constant<NW>) with the compiled
+// shape of candidate v of z class c (the default when v is not a candidate).
+template <class F>
+inline void bwz_dispatch(int c, int v, F&& f) {
+  using std::integral_constant;
+  if (!bwz_valid(c, v)) v = 0;
+  switch (c * kBWZ_NV + v) {
+    case 0: f(integral_constant<int, 3>{}, integral_constant<int, 1>{}); break;
+    case 1: f(integral_constant<int, 3>{}, integral_constant<int, 2>{}); break;
+    case 3: f(integral_constant<int, 4>{}, integral_constant<int, 1>{}); break;
+    case 4: f(integral_constant<int, 3>{}, integral_constant<int, 2>{}); break;
+    case 6: f(integral_constant<int, 5>{}, integral_constant<int, 1>{}); break;
+    case 7: f(integral_constant<int, 3>{}, integral_constant<int, 2>{}); break;
+    case 9: f(integral_constant<int, 4>{}, integral_constant<int, 2>{}); break;
+    case 10: f(integral_constant<int, 8>{}, integral_constant<int, 1>{}); break;
+    default: f(integral_constant<int, 3>{}, integral_constant<int, 3>{}); break;
+  }
+}
 
 __host__ __device__ inline int batch_strip_zshape(int nz) {
   for (int s = 0; s < 4; ++s)
@@ -285,6 +312,7 @@ struct BSweepArgs {
   double* T;
   double* prof;
   int npts;
+  int zvar[4];         // candidate shape of each z class
 };
 
 // One workgroup per instance: prologue into its own scratch area and
@@ -295,7 +323,7 @@ __global__ void __launch_bounds__(256) k_bsetup(BSweepArgs a) {
   double* dA = a.rhs + a.rhs_off[i];
   double* dB = dA + batch_strip_doubles(I.P.nr, I.P.nz);
   batch_strip_prologue(I, a.aux + (long)i * a.lay.stride, a.lay, dA, dB, &a.args[i], &a.args[a.n + i],
-                       kBWZ_G[I.zss], kBWZ_M[I.zss]);
+                       64 * kBWZ_W[I.zss][a.zvar[I.zss]], kBWZ_CM[I.zss][a.zvar[I.zss]]);
   if (threadIdx.x == 0) {
     a.args[2 * a.n + i] = a.args[a.n + i];
     a.args[2 * a.n + i].xout = a.T + I.toff;
@@ -350,8 +378,13 @@ inline BatchLayout batch_layout(long maxcells, long maxstrip) {
   // tables sized for both kernel families (rows layout, strip layout)
   const long rGM = std::max((long)kBR_G * kBR_M[3], (long)kBS_G * kBSR_M);
   long zGM = std::max((long)kBZ_G * kBZ_M[3], (long)kBS_G * kBSZ_M[3]);
-  for (int c = 0; c < 4; ++c) zGM = std::max(zGM, (long)kBWZ_G[c] * kBWZ_M[c]);
-  const long rG = std::max(kBR_G, kBS_G), zG = std::max(std::max(kBZ_G, kBS_G), kBWZ_G[3]);
+  long zG = std::max(kBZ_G, kBS_G);
+  for (int c = 0; c < 4; ++c)
+    for (int v = 0; v < kBWZ_NV; ++v) {
+      zGM = std::max(zGM, 64L * kBWZ_W[c][v] * kBWZ_CM[c][v]);
+      zG = std::max(zG, 64L * kBWZ_W[c][v]);
+    }
+  const long rG = std::max(kBR_G, kBS_G);
   L.dA = put(8 * std::max(maxcells, maxstrip));
   L.dB = put(8 * std::max(maxcells, maxstrip));
   L.geo = put(8 * (3 * (kMaxNr + 1) + 3 * (kMaxNz + 1)));
@@ -370,7 +403,9 @@ inline BatchLayout batch_layout(long maxcells, long maxstrip) {
   L.zxc = put(8 * 4 * kMaxNz);
   long work = std::max(std::max(assemble_work(kBR_G, kBR_M[3]), assemble_work(kBZ_G, kBZ_M[3])),
                        std::max(assemble_work(kBS_G, kBSR_M), assemble_work(kBS_G, kBSZ_M[3])));
-  for (int c = 0; c < 4; ++c) work = std::max(work, assemble_work(kBWZ_G[c], kBWZ_M[c]));
+  for (int c = 0; c < 4; ++c)
+    for (int v = 0; v < kBWZ_NV; ++v)
+      if (bwz_valid(c, v)) work = std::max(work, assemble_work(64 * kBWZ_W[c][v], kBWZ_CM[c][v]));
   L.work = put(8 * work);
   L.stride = off;
   return L;

@@ -109,6 +109,8 @@ _SIGS = {
     "adi_batch_set_materials": [_vp, _dp, _dp, _dp],
     "adi_batch_set_initial": [_vp, _dp],
     "adi_batch_set_launch": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "adi_batch_zshape_info": [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p],
+    "adi_batch_set_zshape": [_vp, ctypes.c_int32, ctypes.c_int32],
     "adi_batch_step": [_vp, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp],
     "adi_batch_sync": [_vp],
     "adi_batch_read_profiles": [_vp, ctypes.c_int32, _dp, ctypes.c_size_t],
@@ -418,6 +420,11 @@ class Batch:
         check(lib().adi_batch_set_launch(self._h, int(lines_per_lane), int(waves_per_block),
                                          int(blocks_per_cu)))
 
+    def set_zshape(self, zclass, variant):
+        """Shape `variant` of batch_zshapes()[zclass] for the z lines of that
+        class in the batched sweep launches (from the next step on)."""
+        check(lib().adi_batch_set_zshape(self._h, int(zclass), int(variant)))
+
     def step(self, dt, nsteps, snapshot_every=0, npts=64, out=None):
         """Advance every instance from its initial field.  out: None, or a
         float64 CUDA tensor of n * (nsteps // snapshot_every) * npts elements
@@ -630,6 +637,23 @@ def layout_shapes(layout, direction):
     buf = (ctypes.c_int32 * max(1, 5 * n.value))()
     check(lib().adi_layout_shapes(LAYOUTS[layout], int(direction), buf, n.value, ctypes.byref(n)))
     return [tuple(buf[5 * i:5 * i + 5]) for i in range(n.value)]
+
+
+def batch_zshapes():
+    """Per z class of the batched sweep launches (columns up to 192, 256,
+    320, 512 rows): {"max_rows": rows, "shapes": [(waves, cells per chunk),
+    ...]}, the first shape the default."""
+    out = []
+    for c in range(4):
+        shapes, rows = [], 0
+        w, m, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        v = 0
+        while lib().adi_batch_zshape_info(c, v, ctypes.byref(w), ctypes.byref(m), ctypes.byref(r)) == 0:
+            shapes.append((w.value, m.value))
+            rows = r.value
+            v += 1
+        out.append({"max_rows": rows, "shapes": shapes})
+    return out
 
 
 def version():

@@ -4,8 +4,10 @@
 // library's instance set-up kernel and, per step, its r launches (every row
 // slot width) and z launches (every z shape) over all instances, with the
 // library's own host plan of workgroup maps, and writes the final fields
-// (each nz*nr doubles, r fastest, in instance order) to argv[2].
+// (each nz*nr doubles, r fastest, in instance order) to argv[2].  argv[3..6]:
+// the z shape of each z class (default 0).
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "hip/hip_runtime.h"
@@ -62,6 +64,10 @@ int main(int argc, char** argv) {
   a.T = T.data();
   a.prof = nullptr;
   a.npts = 64;
+  for (int c = 0; c < 4; ++c) {
+    a.zvar[c] = argc > 3 + c ? atoi(argv[3 + c]) : 0;
+    if (!bwz_valid(c, a.zvar[c])) return 2;
+  }
   emu_launch(n, 256, [&] { k_bsetup(a); });
   for (int st = 1; st <= nsteps; ++st) {
     for (int w = 0; w < 3; ++w) {
@@ -75,11 +81,10 @@ int main(int argc, char** argv) {
     for (int c = 0; c < 4; ++c) {
       if (!plan.nmap_z[c]) continue;
       a.map = plan.map.data() + plan.zmap_off[c];
-      constexpr int W3 = kBWZ_G[3] / 64;
-      if (c == 0) emu_launch(plan.nmap_z[c], 64, [&] { k_bsweep_z<kBWZ_M[0], 1>(a, snap); });
-      else if (c == 1) emu_launch(plan.nmap_z[c], 64, [&] { k_bsweep_z<kBWZ_M[1], 1>(a, snap); });
-      else if (c == 2) emu_launch(plan.nmap_z[c], 64, [&] { k_bsweep_z<kBWZ_M[2], 1>(a, snap); });
-      else emu_launch(plan.nmap_z[c], 64 * W3, [&] { k_bsweep_z<kBWZ_M[3], W3>(a, snap); });
+      bwz_dispatch(c, a.zvar[c], [&](auto m, auto nw) {
+        constexpr int M = decltype(m)::value, NW = decltype(nw)::value;
+        emu_launch(plan.nmap_z[c], 64 * NW, [&] { k_bsweep_z<M, NW>(a, snap); });
+      });
     }
   }
   FILE* o = fopen(argv[2], "wb");

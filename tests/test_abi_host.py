@@ -40,6 +40,23 @@ def test_launch_shapes_listed(native):
         assert r >= 1 and 64 * wpl * ngw <= 1024
 
 
+def test_batch_z_shapes_listed(native):
+    """Every candidate z shape of the batched sweep launches covers the
+    longest columns of its class, the batch's largest grid included."""
+    classes = native.batch_zshapes()
+    assert [c["max_rows"] for c in classes] == [192, 256, 320, 512]
+    for cl in classes:
+        assert len(cl["shapes"]) >= 2 and len(set(cl["shapes"])) == len(cl["shapes"])
+        for waves, cells in cl["shapes"]:
+            assert waves in (1, 2, 3) and cells >= 3
+            assert 64 * waves * cells >= min(cl["max_rows"], 480)
+    w = ctypes.c_int32(-7)
+    assert native.lib().adi_batch_zshape_info(0, 9, ctypes.byref(w), ctypes.byref(ctypes.c_int32()),
+                                              ctypes.byref(ctypes.c_int32())) == native.ADI_EINVAL
+    assert w.value == -7
+    assert native.lib().adi_batch_zshape_info(1, 0, None, None, None) == native.ADI_EINVAL
+
+
 def test_status_strings(native):
     lib = native.lib()
     for code in range(0, -8, -1):

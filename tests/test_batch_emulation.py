@@ -1,5 +1,6 @@
 """The batched sweep launches of the ragged batch (set-up kernel, r sweeps
-with 4, 2 or 1 row groups per wave, z sweeps on one or two waves per line;
+with 4, 2 or 1 row groups per wave, z sweeps in every compiled shape of
+each z class, on one, two or three waves per line;
 paper_1912_03744_amd/csrc/batch.hpp with the library's own host plan of
 workgroup maps), compiled for the host with the stand-in for the HIP device
 environment (tests/emu/shim), against the oracle run on every instance
@@ -44,7 +45,7 @@ def _specs(scheme):
     return specs
 
 
-def _run(emu, tmp_path, specs, scheme, dt, steps):
+def _run(emu, tmp_path, specs, scheme, dt, steps, zshape=(0, 0, 0, 0)):
     inp = tmp_path / "batch.txt"
     out = tmp_path / "T.bin"
     with open(inp, "w") as f:
@@ -54,7 +55,7 @@ def _run(emu, tmp_path, specs, scheme, dt, steps):
             f.write(" ".join(repr(float(x)) for x in list(s.h) + list(s.t_inf)) + "\n")
             f.write(" ".join(repr(float(x)) for x in list(s.k) + list(s.rhoc) + list(s.q)) + "\n")
             f.write("%r\n" % float(s.T0))
-    subprocess.run([str(emu), str(inp), str(out)], check=True, timeout=600)
+    subprocess.run([str(emu), str(inp), str(out)] + [str(v) for v in zshape], check=True, timeout=600)
     flat = np.fromfile(out)
     fields, o = [], 0
     for s in specs:
@@ -64,11 +65,17 @@ def _run(emu, tmp_path, specs, scheme, dt, steps):
     return fields
 
 
-@pytest.mark.parametrize("scheme", ["pr", "lod"])
-def test_batched_sweeps_match_oracle(emu, tmp_path, scheme):
+# z shape per z class: the defaults, then every other compiled candidate
+# (two waves of 3-cell chunks in classes 0-2; one wave of 8-cell chunks and
+# three waves of 3-cell chunks in class 3)
+ZSHAPES = [("pr", (0, 0, 0, 0)), ("lod", (0, 0, 0, 0)), ("pr", (1, 1, 1, 1)), ("pr", (0, 0, 0, 2))]
+
+
+@pytest.mark.parametrize("scheme,zshape", ZSHAPES, ids=["%s-z%d%d%d%d" % ((s,) + z) for s, z in ZSHAPES])
+def test_batched_sweeps_match_oracle(emu, tmp_path, scheme, zshape):
     specs = _specs(scheme)
     steps, dt = 3, specs[0].dt
-    got = _run(emu, tmp_path, specs, scheme, dt, steps)
+    got = _run(emu, tmp_path, specs, scheme, dt, steps, zshape)
     for i, s in enumerate(specs):
         P = oracle.Problem.from_spec(s)
         want, _ = P.step(P.initial(s.T0), scheme, dt, steps)

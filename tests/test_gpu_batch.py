@@ -65,6 +65,34 @@ def test_batch_odd_sizes_and_launch_shapes():
             assert rel_inf(b.field(int(i)), w, P.active()) <= TOL, (shape, i, specs[i].nr, specs[i].nz)
 
 
+def test_batch_z_shapes_per_class():
+    """Every compiled z shape of every z class of the batched sweep launches
+    (odd sizes in each class and columns of each class's longest length)
+    against the oracle; shapes out of range are refused."""
+    from paper_1912_03744_amd import native
+    classes = native.batch_zshapes()
+    assert [c["max_rows"] for c in classes] == [192, 256, 320, 512]
+    assert all(len(c["shapes"]) >= 2 for c in classes)
+    sizes = [(5, 7), (64, 160), (33, 192), (96, 240), (40, 256), (7, 193), (128, 320), (61, 257),
+             (192, 480), (65, 321), (9, 479), (100, 300)]
+    base = W.ragged_batch(len(sizes), master_seed=13, nsteps=10)
+    specs = [s.replace(nr=nr, nz=nz) for s, (nr, nz) in zip(base, sizes)]
+    want = [_oracle_run(s, 10) for s in specs]
+    b = native.Batch(specs)
+    b.set_launch(4, 1, 1)
+    for v in range(max(len(c["shapes"]) for c in classes)):
+        for c, cl in enumerate(classes):
+            b.set_zshape(c, v if v < len(cl["shapes"]) else 0)
+        b.step(1e-3, 10)
+        for i, s in enumerate(specs):
+            P, w = want[i]
+            assert rel_inf(b.field(i), w, P.active()) <= TOL, (v, i, s.nr, s.nz)
+    for c, v in ((0, len(classes[0]["shapes"])), (4, 0), (-1, 0), (3, -1)):
+        with pytest.raises(native.AdiError):
+            b.set_zshape(c, v)
+    b.close()
+
+
 def test_batch_equals_single_instance_path():
     """Instance k of a batch reaches the single-instance GPU result (same
     method, different launch decomposition) to the parity tolerance."""
@@ -131,7 +159,7 @@ def test_batch_full_size_stratified(tmp_path, monkeypatch):
     specs = W.ragged_batch(4096, master_seed=0, scheme="pr", dt=1e-3, nsteps=2000)
     b = native.Batch(specs, scheme="pr")
     tuned = autotune.apply_batch(b, 1e-3, "pr", nsteps=50)
-    print("batch tuned shape %s" % (tuned["shape"],), flush=True)
+    print("batch tuned shape %s, z shapes %s" % (tuned["shape"], tuned.get("zshape")), flush=True)
     b.step(1e-3, 2000, snapshot_every=1000, npts=64)
     prof = b.profiles()
     picks = []
