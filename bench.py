@@ -26,8 +26,8 @@ Prints one JSON line:
               launches, whichever the autotuner picks; cell-updates/s and the
               algorithmic bandwidth (32 B per active cell per step)
 Usage: python bench.py [--gpus 1] [--steps 10000] [--warmup 200] [--no-batch]
-       python bench.py --counter-workload          (the program profiled for traffic)
-       python bench.py --summarize-counters DIR    (rocprofv3 --pmc output -> profiles/)
+       python bench.py --counter-workload [batch]        (the program profiled for traffic)
+       python bench.py --summarize-counters DIR [batch]  (rocprofv3 --pmc output -> profiles/)
 """
 from __future__ import annotations
 
@@ -48,32 +48,44 @@ BYTES_PER_CELL_HALF_STEP = 16
 # The sources the production sweeps are built and launched from: the counter
 # readings stay valid while these are unchanged.
 SWEEP_SOURCES = ("common.hpp", "device.hpp", "strip.hpp", "solver.hip")
+# ... and those of the batch's batched sweep launches.
+BATCH_SOURCES = ("common.hpp", "device.hpp", "strip.hpp", "batch.hpp", "batch.hip")
 
 
-def source_digest():
-    """Hash of the HIP sources of the production sweeps, to tie stored
-    counter readings to a build."""
+def source_digest(files=SWEEP_SOURCES):
+    """Hash of HIP sources (by default those of the production sweeps), to
+    tie stored counter readings to a build."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1912_03744_amd", "csrc")
-    for f in SWEEP_SOURCES:
+    for f in files:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current sources; else None."""
-    path = os.path.join(ROOT, "profiles", "sweep_counters_production_1024x2560.json")
+def _stored(path, files):
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_digest") != source_digest():
-        return None
-    k = rec.get("kernels", {}).get(kernel)
+    return rec if rec.get("source_digest") == source_digest(files) else None
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current sources; else None."""
+    rec = _stored(COUNTERS_JSON, SWEEP_SOURCES)
+    k = None if rec is None else rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def stored_batch_traffic():
+    """HBM bytes per step of the batch's batched sweep launches (every r and
+    z launch of one step) from the committed counter summary, if it was taken
+    on the current sources; else None."""
+    rec = _stored(BATCH_COUNTERS_JSON, BATCH_SOURCES)
+    return None if rec is None else rec.get("hbm_bytes_per_step")
 
 
 def host_threads():
@@ -175,20 +187,27 @@ def batch_leg(n, steps, tune=True, shape=(2, 8, 1)):
            "zshape": {"variant_per_class": zshape,
                       "shapes": [list(native.batch_zshapes()[c]["shapes"][v]) for c, v in enumerate(zshape)]},
            "roofline": {"bound": "hbm", "kernel": "batch", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": stored_batch_traffic() if shape == (4, 1, 1) and zshape == [0, 0, 0, 0] else None,
+                        "traffic_unit": "HBM bytes per step (every r and z launch of one step)",
+                        "alg_bytes_per_step": 2 * BYTES_PER_CELL_HALF_STEP * active}}
     b.close()
     return out
 
 
 COUNTER_COPY_BYTES = 64 << 20
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "sweep_counters_production_1024x2560.json")
+BATCH_COUNTERS_JSON = os.path.join(ROOT, "profiles", "batch_counters_ragged_4096.json")
+BATCH_COUNTER_STEPS = 10
 
 
-def counter_workload(seed):
+def counter_workload(seed, batch=False):
     """The program profiled for HBM traffic (one rocprofv3 --pmc pass per
     counter): a plain copy of COUNTER_COPY_BYTES (torch.neg, read once and
     written once) to calibrate the counters, then 20 launches of each sweep
-    of the production grid in the benchmark's layout and shapes."""
+    of the production grid in the benchmark's layout and shapes, or (batch)
+    BATCH_COUNTER_STEPS steps of the benchmark's 4096-design batch as
+    batched sweep launches in the default z shapes."""
     import torch
 
     from paper_1912_03744_amd import autotune, native
@@ -199,6 +218,15 @@ def counter_workload(seed):
     for _ in range(3):
         torch.neg(src, out=dst)
     torch.cuda.synchronize()
+    if batch:
+        specs = W.ragged_batch(4096, master_seed=seed, scheme="pr", dt=1e-3, nsteps=BATCH_COUNTER_STEPS)
+        b = native.Batch(specs, scheme="pr")
+        b.set_launch(4, 1, 1)
+        b.step(specs[0].dt, BATCH_COUNTER_STEPS)
+        b.sync()
+        print("counter workload done: batch of %d, %d steps" % (len(specs), BATCH_COUNTER_STEPS), flush=True)
+        b.close()
+        return
     spec = W.production(seed)
     p = native.Problem.from_spec(spec)
     autotune.apply(p, spec.dt, spec.scheme)
@@ -207,14 +235,29 @@ def counter_workload(seed):
     print("counter workload done: layout %s r %s z %s" % (p.layout(), p.get_launch(0), p.get_launch(1)), flush=True)
 
 
-def summarize_counters(root):
+def summarize_counters(root, batch=False):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the sweeps from two
     rocprofv3 --pmc runs of counter_workload (root/fetch, root/write), scaled
     by what the same counters read for the calibration copy, into
-    COUNTERS_JSON."""
+    COUNTERS_JSON; or (batch) those of each batched-sweep kernel and their
+    sum over one step, into BATCH_COUNTERS_JSON."""
     import csv
     import glob
     import re
+
+    def name_of(k):
+        if "neg" in k:
+            return "copy"
+        if batch:
+            # demangled (k_bsweep_z<4, 2>) or mangled (k_bsweep_zILi4ELi2E) names
+            m = (re.search(r"k_bsweep_([rz])<(\d+)(?:,\s*(\d+))?>", k) or
+                 re.search(r"k_bsweep_([rz])ILi(\d+)E(?:Li(\d+)E)?", k))
+            return None if m is None else "batch_%s<%s>" % (m.group(1), ",".join(g for g in m.groups()[1:] if g))
+        if re.search(r"k_sweep_rs", k):
+            return "sweep_r"
+        if re.search(r"k_sweep_zs|k_sweepILi", k):
+            return "sweep_z" if "zs" in k else "sweep_rows"
+        return None
 
     def means(pattern):
         out = {}
@@ -223,31 +266,29 @@ def summarize_counters(root):
             raise SystemExit("no counter_collection.csv under %s" % os.path.join(root, pattern))
         for f in files:
             for row in csv.DictReader(open(f)):
-                k = row["Kernel_Name"]
-                if "neg" in k:
-                    name = "copy"
-                elif re.search(r"k_sweep_rs", k):
-                    name = "sweep_r"
-                elif re.search(r"k_sweep_zs|k_sweepILi", k):
-                    name = "sweep_z" if "zs" in k else "sweep_rows"
-                else:
-                    continue
-                out.setdefault(name, []).append(float(row["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in out.items()}
+                name = name_of(row["Kernel_Name"])
+                if name is not None:
+                    out.setdefault(name, []).append(float(row["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in out.items()}
     fetch, write = means("fetch"), means("write")
-    f_scale = COUNTER_COPY_BYTES / (fetch["copy"] * 1024.0)
-    w_scale = COUNTER_COPY_BYTES / (write["copy"] * 1024.0)
-    rec = {"source_digest": source_digest(),
-           "calibration": {"copy_bytes": COUNTER_COPY_BYTES, "copy_fetch_kib": fetch["copy"],
-                           "copy_write_kib": write["copy"], "fetch_scale": f_scale, "write_scale": w_scale},
+    f_scale = COUNTER_COPY_BYTES / (fetch["copy"][0] * 1024.0)
+    w_scale = COUNTER_COPY_BYTES / (write["copy"][0] * 1024.0)
+    rec = {"source_digest": source_digest(BATCH_SOURCES if batch else SWEEP_SOURCES),
+           "calibration": {"copy_bytes": COUNTER_COPY_BYTES, "copy_fetch_kib": fetch["copy"][0],
+                           "copy_write_kib": write["copy"][0], "fetch_scale": f_scale, "write_scale": w_scale},
            "kernels": {}}
-    for k in ("sweep_r", "sweep_z"):
+    names = sorted(k for k in fetch if k != "copy") if batch else ("sweep_r", "sweep_z")
+    for k in names:
         if k in fetch and k in write:
-            fb = fetch[k] * 1024.0 * f_scale
-            wb = write[k] * 1024.0 * w_scale
-            rec["kernels"][k] = {"fetch_kib": fetch[k], "write_kib": write[k], "fetch_bytes": fb,
-                                 "write_bytes": wb, "hbm_bytes_per_launch": fb + wb}
-    with open(COUNTERS_JSON, "w") as f:
+            fb = fetch[k][0] * 1024.0 * f_scale
+            wb = write[k][0] * 1024.0 * w_scale
+            rec["kernels"][k] = {"fetch_kib": fetch[k][0], "write_kib": write[k][0], "fetch_bytes": fb,
+                                 "write_bytes": wb, "hbm_bytes_per_launch": fb + wb, "dispatches": fetch[k][1]}
+    if batch:
+        # every batched-sweep kernel runs once per step
+        rec["steps"] = BATCH_COUNTER_STEPS
+        rec["hbm_bytes_per_step"] = sum(v["hbm_bytes_per_launch"] for v in rec["kernels"].values())
+    with open(BATCH_COUNTERS_JSON if batch else COUNTERS_JSON, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
 
@@ -396,10 +437,10 @@ def nonlinear_leg(t_end, cpu_steps, cpu=True):
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--counter-workload":
-        counter_workload(0)
+        counter_workload(0, batch=sys.argv[2:3] == ["batch"])
         return
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-counters":
-        summarize_counters(sys.argv[2])
+        summarize_counters(sys.argv[2], batch=sys.argv[3:4] == ["batch"])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -314,7 +314,7 @@ def spearman(a, b):
 
 def run(n_train=32768, n_val=2048, n_test=4096, n_sweep=1 << 20, top_frac=0.01, epochs=30, n_recall=16384,
         n_plain=64, log=print, seed=0):
-    """Train the surrogate on batched FP64 solves, calibrate the gate, judge
+    """Train the surrogate on batched FP64 solves, calibrate the gate, measure
     it on held-out solves, then run the screened sweep against the solver."""
     import torch
     with torch.cuda.stream(pipeline_stream()):
@@ -345,7 +345,7 @@ def _run(n_train, n_val, n_test, n_sweep, top_frac, epochs, n_recall, n_plain, l
     res["train_pairs"] = len(Xtr)
     res["calibration"] = calibrate(sur, Xva, Yva)
     log("calibration %s" % res["calibration"])
-    # held-out judgement, every snapshot time
+    # held-out errors, every snapshot time
     P = sur.predict(Xte)
     err = rel_profile_error(sur.profile(P), Yte)
     ok = sur.gate(Xte[:, :11].astype(np.float64), P)

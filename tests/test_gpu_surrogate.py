@@ -1,6 +1,6 @@
 """End-to-end surrogate path at a small scale: labels from the batched FP64
 solver, ensemble training on the matrix-core kernels, gate calibration, the
-held-out judgement and the screened sweep against the plain and batched
+held-out errors and the screened sweep against the plain and batched
 solvers.
 
 Checks, beyond the bookkeeping:
