@@ -242,6 +242,28 @@ def test_production_benchmark_configuration_full_length(tmp_path, monkeypatch):
     assert e["residual"] < 1e-12
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_production_other_seeds(tmp_path, monkeypatch, seed):
+    """The production grid with the other seeded material sets (seeds 1 and
+    2 of the benchmark's generator), in the benchmark's configuration
+    (autotuned layout and shapes, graphs of 100 steps, checks every 100):
+    full-field parity with the oracle after 300 steps."""
+    from paper_1912_03744_amd import autotune, native
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "tune.json"))
+    s = W.production(seed)
+    P = oracle.Problem.from_spec(s)
+    want, _ = P.step_threads(P.initial(s.T0), s.scheme, s.dt, 300, _host_threads())
+    p = native.Problem.from_spec(s)
+    autotune.apply(p, s.dt, s.scheme)
+    p.set_check(100, 1e-9)
+    p.set_graph_steps(100)
+    p.step(s.dt, 300)
+    err = rel_inf(p.read_field(), want, P.active())
+    _say("production seed %d: 300 steps, rel err %.3e" % (seed, err))
+    assert err <= TOL
+    assert p.energy()["residual"] < 1e-11
+
+
 def test_graph_and_checks_do_not_change_results():
     s = W.production(1, nr=200, nz=500)
     _say("graph vs plain")
