@@ -151,7 +151,7 @@ def _host_threads():
 @pytest.mark.timeout(900)
 def test_batch_full_size_stratified(tmp_path, monkeypatch):
     """The benchmark's batch: 4096 instances, 2000 steps, in the launch shape
-    the autotuner picks; 8 instances per size class (32 in all, spread over
+    the autotuner picks; 16 instances per size class (64 in all, spread over
     the batch: the first, the last and evenly between) against the oracle run
     alone (field and terminal-face profile at t = 1 and 2)."""
     from paper_1912_03744_amd import autotune, native
@@ -165,9 +165,9 @@ def test_batch_full_size_stratified(tmp_path, monkeypatch):
     picks = []
     for size in W.BATCH_SIZES:
         idx = [i for i, s in enumerate(specs) if (s.nr, s.nz) == size]
-        sel = np.unique(np.linspace(0, len(idx) - 1, 8).round().astype(int))
+        sel = np.unique(np.linspace(0, len(idx) - 1, 16).round().astype(int))
         picks += [idx[k] for k in sel]
-    assert len(picks) == 32
+    assert len(picks) == 64
     threads = _host_threads()
     for i in picks:
         s = specs[i]
