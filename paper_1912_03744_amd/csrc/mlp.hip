@@ -232,20 +232,27 @@ __global__ void k_encode(const float* __restrict__ x, int nin, long B, const flo
   }
 }
 
-// Mean squared error: dY = 2 (Y - T) / (B * nout), per-row partial sums of
-// squares (reduced in a fixed order by k_sum_rows).
-__global__ void k_loss(const float* __restrict__ Y, const float* __restrict__ T, long B, int nout, float* dY,
-                       __bf16* dYb, float* rowsq) {
-  for (long r = blockIdx.x * (long)blockDim.x + threadIdx.x; r < B; r += (long)gridDim.x * blockDim.x) {
+// Mean squared error: dY = 2 (Y - T) / (B * nout), per-row sums of squares
+// (reduced in a fixed order by k_sum_rows).  One wave per row, lane j on
+// columns j, j + 64, ... (coalesced); the lanes' partial sums are added by a
+// butterfly in a fixed order.
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Y, const float* __restrict__ T, long B,
+                                              int nout, float* dY, __bf16* dYb, float* rowsq) {
+  const int lane = threadIdx.x & 63;
+  const float c = 2.0f / (float)((double)B * nout);
+  const long first = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
+  const long stride = ((long)gridDim.x * blockDim.x) >> 6;
+  for (long r = first; r < B; r += stride) {
     double s = 0.0;
-    const float c = 2.0f / (float)((double)B * nout);
-    for (int j = 0; j < nout; ++j) {
-      const float d = Y[r * nout + j] - T[r * nout + j];
+    for (int j = lane; j < nout; j += 64) {
+      const long e = r * nout + j;
+      const float d = Y[e] - T[e];
       s += (double)d * d;
-      dY[r * nout + j] = c * d;
-      dYb[r * nout + j] = (__bf16)(c * d);
+      dY[e] = c * d;
+      dYb[e] = (__bf16)(c * d);
     }
-    rowsq[r] = (float)s;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) rowsq[r] = (float)s;
   }
 }
 
@@ -262,17 +269,39 @@ __global__ void __launch_bounds__(256) k_sum_rows(const float* v, long n, double
   if (threadIdx.x == 0) out[0] = (float)(s[0] / denom);
 }
 
-// Column sums of D (B x N fp32) into out[N]: one block per 64 columns, four
-// row phases combined in a fixed order.
-__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ D, long B, int N, float* out) {
-  __shared__ float s[4][64];
+// Column sums of D (B x N fp32) in two passes, each in a fixed order: block
+// (x, s) sums rows [s R, s R + R) of 64 columns (four row phases, combined
+// in order) into part[s][c]; k_colsum_final adds the slices in order.
+__global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ D, long B, int N, long R,
+                                                     float* __restrict__ part) {
+  __shared__ float sm[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+  const long r0 = blockIdx.y * R, r1 = r0 + R < B ? r0 + R : B;
   float a = 0.0f;
   if (c < N)
-    for (long r = ph; r < B; r += 4) a += D[r * N + c];
-  s[ph][threadIdx.x & 63] = a;
+    for (long r = r0 + ph; r < r1; r += 4) a += D[r * N + c];
+  sm[ph][threadIdx.x & 63] = a;
   __syncthreads();
-  if (ph == 0 && c < N) out[c] = ((s[0][threadIdx.x] + s[1][threadIdx.x]) + s[2][threadIdx.x]) + s[3][threadIdx.x];
+  if (ph == 0 && c < N)
+    part[(long)blockIdx.y * N + c] = ((sm[0][threadIdx.x] + sm[1][threadIdx.x]) + sm[2][threadIdx.x]) +
+                                     sm[3][threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) k_colsum_final(const float* __restrict__ part, int S, int N,
+                                                      float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  float a = 0.0f;
+  for (int q = 0; q < S; ++q) a += part[(long)q * N + c];
+  out[c] = a;
+}
+
+// Rows per slice of the column sums: at least 64, at most COLSUM_SLICES
+// slices.
+constexpr int COLSUM_SLICES = 256;
+inline long colsum_rows(long B) {
+  const long R = (B + COLSUM_SLICES - 1) / COLSUM_SLICES;
+  return std::max(64L, (R + 3) / 4 * 4);
 }
 
 // Sum the split-K partial products (fixed order) into the gradient of W,
@@ -374,6 +403,7 @@ struct adi_mlp_s {
   float *dUf = nullptr, *dUf2 = nullptr;
   __bf16 *dUb = nullptr, *dUb2 = nullptr;
   float* rowsq = nullptr;
+  float* colpart = nullptr;  // slices of the bias-gradient column sums
   float* part = nullptr;
   long part_cap = 0;
   float* loss = nullptr;
@@ -407,9 +437,9 @@ void free_acts(adi_mlp m) {
     m->H[l] = nullptr;
     m->U[l] = nullptr;
   }
-  void* b[] = {m->Y, m->dYf, m->dYb, m->dUf, m->dUf2, m->dUb, m->dUb2, m->rowsq};
+  void* b[] = {m->Y, m->dYf, m->dYb, m->dUf, m->dUf2, m->dUb, m->dUb2, m->rowsq, m->colpart};
   for (void* p : b) dev_free(p);
-  m->Y = m->dYf = m->dUf = m->dUf2 = m->rowsq = nullptr;
+  m->Y = m->dYf = m->dUf = m->dUf2 = m->rowsq = m->colpart = nullptr;
   m->dYb = m->dUb = m->dUb2 = nullptr;
   m->cap = 0;
 }
@@ -435,6 +465,7 @@ adi_status ensure_acts(adi_mlp m, long B) {
   ADI_TRY(dev_alloc((void**)&m->dUb, 2 * cap * wmax, m->stream));
   ADI_TRY(dev_alloc((void**)&m->dUb2, 2 * cap * wmax, m->stream));
   ADI_TRY(dev_alloc((void**)&m->rowsq, 4 * cap, m->stream));
+  ADI_TRY(dev_alloc((void**)&m->colpart, 4L * COLSUM_SLICES * wmax, m->stream));
   m->cap = cap;
   return ADI_OK;
 }
@@ -496,7 +527,7 @@ adi_status forward(adi_mlp m, const float* x, long B) {
 // Loss, gradients of all parameters into m->Gr.
 adi_status backward(adi_mlp m, const float* target, long B) {
   const int nout = m->width[m->nl];
-  hipLaunchKernelGGL(k_loss, dim3((int)std::min<long>((B + 255) / 256, 4096)), dim3(256), 0, m->stream, m->Y,
+  hipLaunchKernelGGL(k_loss, dim3((int)std::min<long>((B + 3) / 4, 4096)), dim3(256), 0, m->stream, m->Y,
                      target, B, nout, m->dYf, m->dYb, m->rowsq);
   ADI_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, m->stream, m->rowsq, B, (double)B * nout, m->loss);
@@ -536,7 +567,12 @@ adi_status backward(adi_mlp m, const float* target, long B) {
     hipLaunchKernelGGL(k_reduce_splits, dim3((int)std::min<long>((nw + 255) / 256, 2048)), dim3(256), 0,
                        m->stream, m->part, nsplit, (long)kin * no, m->width[l], no, m->Gr + m->woff[l]);
     ADI_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_colsum, dim3((no + 63) / 64), dim3(256), 0, m->stream, dF, B, no, m->Gr + m->boff[l]);
+    const long R = colsum_rows(B);
+    const int S = (int)((B + R - 1) / R);
+    hipLaunchKernelGGL(k_colsum_part, dim3((no + 63) / 64, S), dim3(256), 0, m->stream, dF, B, no, R, m->colpart);
+    ADI_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_colsum_final, dim3((no + 255) / 256), dim3(256), 0, m->stream, m->colpart, S, no,
+                       m->Gr + m->boff[l]);
     ADI_CHECK_LAUNCH();
     if (l == 0) break;
     // dU_{l-1} = (dU_l W_l^T) * gelu'(U_{l-1})
@@ -578,14 +614,19 @@ adi_status launch_layer(adi_mlp m, int epi, const __bf16* A, const __bf16* Wt, c
   return ADI_OK;
 }
 
+// One layer: the weight-resident kernel when the batch gives every CU at
+// least one workgroup of 256 rows (each workgroup first loads the whole
+// layer's weights into LDS), else the tiled GEMM (64 x 64 output tiles, as
+// many as the batch has).
 adi_status layer_forward(adi_mlp m, int l, int epi, const __bf16* in, long B, float* of, __bf16* ob) {
   const int kd = m->kin_pad[l], nd = m->width[l + 1];
   const float* bias = m->P + m->boff[l];
-  if (kd == 64 && nd == 256) return launch_layer<64, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
-  if (kd == 256 && nd == 256) return launch_layer<256, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
-  if (kd == 256 && nd == 64) return launch_layer<256, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
-  if (kd == 256 && nd == 128) return launch_layer<256, 128>(m, epi, in, m->Wtb[l], bias, B, of, ob);
-  if (kd == 64 && nd == 64) return launch_layer<64, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  const bool resident = B >= 256L * m->cus;
+  if (resident && kd == 64 && nd == 256) return launch_layer<64, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (resident && kd == 256 && nd == 256) return launch_layer<256, 256>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (resident && kd == 256 && nd == 64) return launch_layer<256, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (resident && kd == 256 && nd == 128) return launch_layer<256, 128>(m, epi, in, m->Wtb[l], bias, B, of, ob);
+  if (resident && kd == 64 && nd == 64) return launch_layer<64, 64>(m, epi, in, m->Wtb[l], bias, B, of, ob);
   GemmArgs g{};
   g.A = in;
   g.lda = kd;

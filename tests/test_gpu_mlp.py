@@ -64,6 +64,32 @@ def test_forward_matches_oracle(widths):
     assert _rel(got, plain) <= 1e-2 and _cos(got, plain) >= 0.999
 
 
+@pytest.mark.parametrize("widths", [WIDTHS, [12, 256, 256, 256, 256, 128]], ids=["surrogate64", "surrogate128"])
+def test_forward_large_batch_sampled_rows(widths):
+    """A batch that gives every CU a workgroup of 256 rows takes the
+    weight-resident layer kernels (smaller batches the tiled GEMM): 65,600
+    rows (a ragged last workgroup) against the oracle on 1,024 sampled rows,
+    the first and last included, and the tiled GEMM's output on the first
+    4,096 rows as a batch of its own to the same tolerance."""
+    import torch
+    B = 65600
+    net, xd, td, ps, xe, t, _ = _setup(widths, 3, B)
+    y = torch.empty(B, widths[-1], device="cuda")
+    net.forward(xd, y)
+    got = y.cpu().numpy().astype(np.float64)
+    rows = np.unique(np.concatenate([[0, B - 1], np.random.default_rng(3).choice(B, 1022, replace=False)]))
+    emu, _ = O.forward(ps, xe[rows], round_hidden=O.bf16_round)
+    plain, _ = O.forward(ps, xe[rows])
+    print("large batch forward rel l2 vs rounded ref %.2e, vs fp64 ref %.2e"
+          % (_rel(got[rows], emu), _rel(got[rows], plain)), flush=True)
+    assert _rel(got[rows], emu) <= 3e-3
+    assert _rel(got[rows], plain) <= 1e-2 and _cos(got[rows], plain) >= 0.999
+    y2 = torch.empty(4096, widths[-1], device="cuda")
+    net.forward(xd[:4096].contiguous(), y2)
+    small = y2.cpu().numpy().astype(np.float64)
+    assert _rel(small, got[:4096]) <= 3e-3
+
+
 @pytest.mark.parametrize("widths", [[12, 64, 64], WIDTHS], ids=["small", "surrogate"])
 def test_gradients_match_oracle(widths):
     net, xd, td, ps, xe, t, _ = _setup(widths, 2, 1024)
