@@ -20,6 +20,8 @@ Prints one JSON line:
               OpenMP threads, as in the paper; single-threaded figure beside)
   single_layout  secondary figure: the 64x160 layout of Fig. 1, 1000 steps
               (latency-bound; microseconds per step)
+  surrogate_training  secondary figure: Adam steps of the surrogate's network
+              (batch 4096), samples/s and the matrix-core fraction
   batch       secondary figure: the ragged design batch (4096 seeded
               instances of 64x160 ... 192x480 cells, 2000 PR steps of 1e-3)
               as captured graphs: a persistent kernel or batched sweep
@@ -370,6 +372,47 @@ def surrogate_leg(batch=65536, reps=50):
                          "traffic": None}}
 
 
+def training_leg(batch=4096, steps=300):
+    """Surrogate training on the matrix cores: `steps` Adam steps (forward,
+    backward, update, bf16 weight refresh) of the surrogate's network on
+    batches of `batch` seeded rows, timed with HIP events on the network's
+    stream; samples/s and the products' rate (three times the forward's
+    flops per sample: forward, input gradient, weight gradient) against the
+    dense bf16 MFMA peak."""
+    import torch
+
+    from paper_1912_03744_amd import native
+    from paper_1912_03744_amd import surrogate as S
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        net = native.MLP(S.WIDTHS, seed=6)
+        shift, scale = S.feature_scaling()
+        net.set_scaling(shift, scale)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        X = torch.rand(16 * batch, 12, device="cuda", generator=g)
+        Y = torch.rand(16 * batch, S.WIDTHS[-1], device="cuda", generator=g)
+        for it in range(20):
+            net.train_step(X[(it % 16) * batch:(it % 16 + 1) * batch], Y[(it % 16) * batch:(it % 16 + 1) * batch],
+                           1e-3)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for it in range(steps):
+            net.train_step(X[(it % 16) * batch:(it % 16 + 1) * batch], Y[(it % 16) * batch:(it % 16 + 1) * batch],
+                           1e-3)
+        ev1.record(stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+    tflops = 3 * mlp_flop_per_sample(S.WIDTHS) * batch / (ms * 1e-3) / 1e12
+    net.close()
+    return {"workload": "surrogate training step, 12 -> 4 x 256 (GELU) -> %d, MSE + Adam, batch %d, %d steps, "
+                        "seeded rows" % (S.WIDTHS[-1], batch, steps),
+            "value": batch / (ms * 1e-3), "unit": "samples/s", "us_per_step": ms * 1e3,
+            "roofline": {"bound": "mfma", "kernel": "training step (all kernels)", "achieved": tflops,
+                         "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
+                         "traffic": None}}
+
+
 NL_BYTES_PER_CELL_SOLVE = 32  # per line solve: iterate, current layer and explicit part read, new iterate written
 
 
@@ -466,6 +509,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="run only the surrogate inference leg and print its figures")
+    ap.add_argument("--training-only", action="store_true",
+                    help="run only the surrogate training leg and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -481,6 +526,9 @@ def main():
     torch.cuda.set_device(0)
     if args.surrogate_only:
         print(json.dumps(surrogate_leg()), flush=True)
+        return
+    if args.training_only:
+        print(json.dumps(training_leg()), flush=True)
         return
     if args.nonlinear_only:
         print(json.dumps(nonlinear_leg(args.nonlinear_t, args.cpu_nonlinear_steps, cpu=not args.no_cpu)),
@@ -569,6 +617,10 @@ def main():
         out["surrogate"] = surrogate_leg()
         print("bench: surrogate %.3e samples/s, %.1f TFLOP/s" % (out["surrogate"]["value"],
               out["surrogate"]["roofline"]["achieved"]), file=sys.stderr, flush=True)
+        out["surrogate_training"] = training_leg()
+        print("bench: surrogate training %.1f us per step, %.1f TFLOP/s" % (
+            out["surrogate_training"]["us_per_step"], out["surrogate_training"]["roofline"]["achieved"]),
+            file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps, args.cpu_threaded_steps)
         if "batch" in out:

@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(256) k_sum_rows(const float* v, long n, double
 
 // Column sums of D (B x N fp32) in two passes, each in a fixed order: block
 // (x, s) sums rows [s R, s R + R) of 64 columns (four row phases, combined
-// in order) into part[s][c]; k_colsum_final adds the slices in order.
+// in order) into part[s][c]; k_colsum_final adds the slices (below).
 __global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ D, long B, int N, long R,
                                                      float* __restrict__ part) {
   __shared__ float sm[4][64];
@@ -287,13 +287,17 @@ __global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ D
                                      sm[3][threadIdx.x];
 }
 
+// One wave per column: lane q adds slices q, q + 64, ... in order, then the
+// lanes' sums are combined by a butterfly (lane 0's order is fixed).
 __global__ void __launch_bounds__(256) k_colsum_final(const float* __restrict__ part, int S, int N,
                                                       float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
+  const int lane = threadIdx.x & 63;
+  const int c = (int)((blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6);
+  if (c >= N) return;  // whole waves: c is the same in every lane of a wave
   float a = 0.0f;
-  for (int q = 0; q < S; ++q) a += part[(long)q * N + c];
-  out[c] = a;
+  for (int q = lane; q < S; q += 64) a += part[(long)q * N + c];
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+  if (lane == 0) out[c] = a;
 }
 
 // Rows per slice of the column sums: at least 64, at most COLSUM_SLICES
@@ -571,7 +575,7 @@ adi_status backward(adi_mlp m, const float* target, long B) {
     const int S = (int)((B + R - 1) / R);
     hipLaunchKernelGGL(k_colsum_part, dim3((no + 63) / 64, S), dim3(256), 0, m->stream, dF, B, no, R, m->colpart);
     ADI_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_colsum_final, dim3((no + 255) / 256), dim3(256), 0, m->stream, m->colpart, S, no,
+    hipLaunchKernelGGL(k_colsum_final, dim3((no + 3) / 4), dim3(256), 0, m->stream, m->colpart, S, no,
                        m->Gr + m->boff[l]);
     ADI_CHECK_LAUNCH();
     if (l == 0) break;
