@@ -367,7 +367,7 @@ def surrogate_leg(batch=65536, reps=50):
     return {"workload": "surrogate forward pass, 12 -> 4 x 256 (GELU) -> %d, bf16 matrix cores with fp32 "
                         "accumulation, batch %d, seeded inputs over the design box" % (S.WIDTHS[-1], batch),
             "value": batch / (ms * 1e-3), "unit": "samples/s", "ms_per_batch": ms,
-            "roofline": {"bound": "mfma", "kernel": "k_layer (all layers)", "achieved": tflops,
+            "roofline": {"bound": "mfma", "kernel": "k_mlp_fused (whole network)", "achieved": tflops,
                          "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
                          "traffic": None}}
 
