@@ -221,8 +221,8 @@ __global__ void __launch_bounds__(256) k_layer(const __bf16* __restrict__ A, con
 // workgroup takes tiles of 256 rows (64 per wave) and keeps their
 // activations on the CU from the input to the output.  The wave encodes its
 // rows' inputs straight into its A fragments; per layer the workgroup copies
-// W^T into LDS, each wave multiplies as k_layer does (same fragments, same k
-// order, so every value equals the layer-by-layer path's bit for bit), and
+// W^T into LDS, each wave multiplies as k_layer does (the same fragments and
+// k order, and the same epilogue arithmetic as the layer-by-layer path), and
 // for a hidden layer writes bias + GELU as bf16 into LDS (the weights'
 // space, no longer needed), from where it reads its A fragments of the next
 // layer; the output layer stores bias + product as fp32.  Activations never
