@@ -218,15 +218,18 @@ __global__ void __launch_bounds__(256) k_layer(const __bf16* __restrict__ A, con
 
 // The whole inference forward pass of a network whose hidden layers are 256
 // wide (input padded to KPAD = 64, output NOUT), in one kernel: each
-// workgroup takes tiles of 256 rows (64 per wave) and keeps their
-// activations on the CU from the input to the output.  The wave encodes its
-// rows' inputs straight into its A fragments; per layer the workgroup copies
-// W^T into LDS, each wave multiplies as k_layer does (the same fragments and
-// k order, and the same epilogue arithmetic as the layer-by-layer path), and
-// for a hidden layer writes bias + GELU as bf16 into LDS (the weights'
-// space, no longer needed), from where it reads its A fragments of the next
-// layer; the output layer stores bias + product as fp32.  Activations never
-// go to HBM: per tile only the inputs are read and the outputs written.
+// workgroup of FUSED_WAVES waves takes tiles of 256 rows (32 per wave) and
+// keeps their activations on the CU from the input to the output.  The wave
+// encodes its rows' inputs straight into its A fragments; per layer the
+// workgroup copies W^T into LDS, each wave multiplies its 32 rows with
+// every 32-column block of W^T (the fragments, k order and epilogue
+// arithmetic of k_layer), and for a hidden layer writes bias + GELU as bf16
+// into LDS (the weights' space, no longer needed), from where it reads its A
+// fragments of the next layer; the output layer stores bias + product as
+// fp32.  Activations never go to HBM: per tile only the inputs are read and
+// the outputs written.  32 rows per wave (one A fragment per k step, 8
+// accumulators) leave room for two waves per SIMD, which hide the latency
+// of the epilogue: 64 rows per wave at one wave per SIMD took 1.6x as long.
 struct FusedArgs {
   const float* x;
   int nin;
@@ -239,110 +242,93 @@ struct FusedArgs {
   float* y;
 };
 
-constexpr int FUSED_LDA = 256 + 8;  // padded LDS rows (bf16): W^T and activations
+constexpr int FUSED_WAVES = 8;
+constexpr int FUSED_ROWS = 32 * FUSED_WAVES;  // rows per tile
+constexpr int FUSED_LDA = 256 + 8;            // padded LDS rows (bf16): W^T and activations
 
-// One layer of k_mlp_fused for the wave's rows m0 .. m0 + 63 (A fragments
-// a0: rows m0 + lr, a1: rows m0 + 32 + lr; first KD/16 used).
+// One layer of k_mlp_fused for the wave's rows m0 .. m0 + 31 (A fragments
+// a: row m0 + lr, k step k in a[k]; the first KD/16 used).
 template <int KD, int ND, bool LAST>
-__device__ __forceinline__ void fused_layer(const FusedArgs& f, int l, long m0, __bf16* lds, bf16x8 (&a0)[16],
-                                            bf16x8 (&a1)[16]) {
+__device__ __forceinline__ void fused_layer(const FusedArgs& f, int l, long m0, __bf16* lds, bf16x8 (&a)[16]) {
   constexpr int LDW = KD + 8, NB = ND / 32, KS = KD / 16;
-  static_assert(ND * LDW <= 256 * FUSED_LDA, "W^T fits the LDS space");
+  static_assert(ND * LDW <= FUSED_ROWS * FUSED_LDA, "W^T fits the LDS space");
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, half = lane >> 5, lr = lane & 31;
   const __bf16* __restrict__ Wt = f.Wt[l];
   const float* __restrict__ bias = f.bias[l];
   __syncthreads();  // every wave is done with the LDS space
-  // unrolled: the copy's loads in flight together, not one latency each (8:
-  // the A fragments are live here)
-#pragma unroll 8
-  for (int q = t; q < ND * KD / 8; q += 256) {
+  // unrolled: the copy's loads in flight together, not one latency each
+#pragma unroll 4
+  for (int q = t; q < ND * KD / 8; q += 64 * FUSED_WAVES) {
     const int n = q / (KD / 8), k8 = q % (KD / 8);
     *(bf16x8*)&lds[n * LDW + 8 * k8] = *(const bf16x8*)(Wt + (long)n * KD + 8 * k8);
   }
   __syncthreads();
-  floatx16 acc0[NB], acc1[NB];
+  floatx16 acc[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      acc0[nb][i] = 0.0f;
-      acc1[nb][i] = 0.0f;
-    }
+    for (int i = 0; i < 16; ++i) acc[nb][i] = 0.0f;
 #pragma unroll
   for (int k = 0; k < KS; ++k)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const bf16x8 b = *(const bf16x8*)&lds[(nb * 32 + lr) * LDW + 16 * k + 8 * half];
-      acc0[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[k], b, acc0[nb], 0, 0, 0);
-      acc1[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[k], b, acc1[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[k], b, acc[nb], 0, 0, 0);
     }
+  // accumulator i of lane l: row 8 (i/4) + 4 (l/32) + i%4, column l%32
   if constexpr (LAST) {
-    // accumulator i of lane l: row 8 (i/4) + 4 (l/32) + i%4, column l%32
 #pragma unroll
-    for (int hb = 0; hb < 2; ++hb)
+    for (int nb = 0; nb < NB; ++nb) {
+      const int n = nb * 32 + lr;
+      const float bn = bias[n];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int n = nb * 32 + lr;
-        const float bn = bias[n];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const long m = m0 + 32 * hb + 8 * (i >> 2) + 4 * half + (i & 3);
-          if (m < f.B) f.y[m * ND + n] = (hb ? acc1[nb][i] : acc0[nb][i]) + bn;
-        }
+      for (int i = 0; i < 16; ++i) {
+        const long m = m0 + 8 * (i >> 2) + 4 * half + (i & 3);
+        if (m < f.B) f.y[m * ND + n] = acc[nb][i] + bn;
       }
+    }
   } else {
     static_assert(ND == 256, "hidden layers are 256 wide");
     __syncthreads();  // every wave has read its W^T fragments
-    __bf16* act = lds + (size_t)wave * 64 * FUSED_LDA;  // the wave's 64 rows
+    __bf16* act = lds + (size_t)wave * 32 * FUSED_LDA;  // the wave's 32 rows
 #pragma unroll
-    for (int hb = 0; hb < 2; ++hb)
+    for (int nb = 0; nb < NB; ++nb) {
+      const int n = nb * 32 + lr;
+      const float bn = bias[n];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int n = nb * 32 + lr;
-        const float bn = bias[n];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = 32 * hb + 8 * (i >> 2) + 4 * half + (i & 3);
-          act[r * FUSED_LDA + n] = (__bf16)gelu_f((hb ? acc1[nb][i] : acc0[nb][i]) + bn);
-        }
+      for (int i = 0; i < 16; ++i) {
+        const int r = 8 * (i >> 2) + 4 * half + (i & 3);
+        act[r * FUSED_LDA + n] = (__bf16)gelu_f(acc[nb][i] + bn);
       }
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      a0[k] = *(const bf16x8*)&act[lr * FUSED_LDA + 16 * k + 8 * half];
-      a1[k] = *(const bf16x8*)&act[(32 + lr) * FUSED_LDA + 16 * k + 8 * half];
-    }
+    for (int k = 0; k < 16; ++k) a[k] = *(const bf16x8*)&act[lr * FUSED_LDA + 16 * k + 8 * half];
   }
 }
 
 template <int NOUT>
-__global__ void __launch_bounds__(256) k_mlp_fused(FusedArgs f) {
-  __shared__ __attribute__((aligned(16))) __bf16 lds[256 * FUSED_LDA];
+__global__ void __launch_bounds__(64 * FUSED_WAVES, 2) k_mlp_fused(FusedArgs f) {
+  __shared__ __attribute__((aligned(16))) __bf16 lds[FUSED_ROWS * FUSED_LDA];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, half = lane >> 5, lr = lane & 31;
-  for (long tile = blockIdx.x; tile * 256 < f.B; tile += gridDim.x) {
-    const long m0 = tile * 256 + wave * 64;
+  for (long tile = blockIdx.x; tile * FUSED_ROWS < f.B; tile += gridDim.x) {
+    const long m0 = tile * FUSED_ROWS + wave * 32;
     // encoded inputs as A fragments (k_encode's arithmetic): features
-    // 16 k + 8 half + e of rows m0 + lr and m0 + 32 + lr, 0 past nin
-    bf16x8 a0[16], a1[16];
+    // 16 k + 8 half + e of row m0 + lr, 0 past nin
+    bf16x8 a[16];
+    const long r = m0 + lr;
 #pragma unroll
     for (int k = 0; k < KPAD / 16; ++k)
 #pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-        const long r = m0 + 32 * hb + lr;
-        bf16x8 v;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int c = 16 * k + 8 * half + e;
-          v[e] = (__bf16)(c < f.nin && r < f.B ? (f.x[r * f.nin + c] - f.shift[c]) * f.scale[c] : 0.0f);
-        }
-        if (hb) a1[k] = v;
-        else a0[k] = v;
+      for (int e = 0; e < 8; ++e) {
+        const int c = 16 * k + 8 * half + e;
+        a[k][e] = (__bf16)(c < f.nin && r < f.B ? (f.x[r * f.nin + c] - f.shift[c]) * f.scale[c] : 0.0f);
       }
-    fused_layer<KPAD, 256, false>(f, 0, m0, lds, a0, a1);
-    for (int l = 1; l < f.nl - 1; ++l) fused_layer<256, 256, false>(f, l, m0, lds, a0, a1);
-    fused_layer<256, NOUT, true>(f, f.nl - 1, m0, lds, a0, a1);
+    fused_layer<KPAD, 256, false>(f, 0, m0, lds, a);
+    for (int l = 1; l < f.nl - 1; ++l) fused_layer<256, 256, false>(f, l, m0, lds, a);
+    fused_layer<256, NOUT, true>(f, f.nl - 1, m0, lds, a);
   }
 }
 
@@ -629,7 +615,7 @@ adi_status layer_forward(adi_mlp m, int l, int epi, const __bf16* in, long B, fl
 // layer l in H[l] (no pre-activations kept), output straight into y.  The
 // same products and epilogue arithmetic as forward().
 adi_status forward_infer(adi_mlp m, const float* x, long B, __bf16* X, __bf16* const* H, float* y) {
-  // the whole pass in one kernel when every CU gets a workgroup of 256 rows
+  // the whole pass in one kernel when every CU gets a tile of 256 rows
   // and the network is 64 (padded input) -> 256 x (nl - 1) -> 64 | 128 | 256
   bool fused = B >= 256L * m->cus && m->nl >= 2 && m->kin_pad[0] == KPAD;
   for (int l = 1; l < m->nl; ++l) fused = fused && m->width[l] == 256;
@@ -648,10 +634,11 @@ adi_status forward_infer(adi_mlp m, const float* x, long B, __bf16* X, __bf16* c
     }
     f.nl = m->nl;
     f.y = y;
-    const int grid = (int)std::min<long>(m->cus, (B + 255) / 256);
-    if (nout == 64) hipLaunchKernelGGL(k_mlp_fused<64>, dim3(grid), dim3(256), 0, m->stream, f);
-    else if (nout == 128) hipLaunchKernelGGL(k_mlp_fused<128>, dim3(grid), dim3(256), 0, m->stream, f);
-    else hipLaunchKernelGGL(k_mlp_fused<256>, dim3(grid), dim3(256), 0, m->stream, f);
+    const int grid = (int)std::min<long>(m->cus, (B + FUSED_ROWS - 1) / FUSED_ROWS);
+    const dim3 block(64 * FUSED_WAVES);
+    if (nout == 64) hipLaunchKernelGGL(k_mlp_fused<64>, dim3(grid), block, 0, m->stream, f);
+    else if (nout == 128) hipLaunchKernelGGL(k_mlp_fused<128>, dim3(grid), block, 0, m->stream, f);
+    else hipLaunchKernelGGL(k_mlp_fused<256>, dim3(grid), block, 0, m->stream, f);
     ADI_CHECK_LAUNCH();
     return ADI_OK;
   }
